@@ -1,0 +1,193 @@
+/*
+ * pms.h -- C ABI of libpms, the gfx950 (MI355X) implementation of
+ * equirectangular PatchMatch-Stereo densification after Surmann, Thurow,
+ * Slomma, "PatchMatch-Stereo-Panorama, a fast dense reconstruction from 360
+ * degree video images" (Sec. III, "Proposed method").
+ *
+ * The problem statement (Sec. III, first paragraph): a keyframe and its
+ * neighbouring keyframes, each an equirectangular 360 degree image with a
+ * 6-DoF pose from SLAM, are turned into a dense 360 degree depth image on the
+ * GPU; once depth maps of further keyframes exist, a consistency filter
+ * removes outliers (Sec. III, paragraph on the densification thread).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Images:  W x H with W == 2H, row-major, one channel, pitch in bytes.
+ *          float32, float16 or uint8 (uint8 is scaled by 1/255; the NCC
+ *          variance floor applies to the scaled values). All images of one
+ *          call have the same W and H.
+ * Camera:  equirectangular, pixel centres on integer coordinates:
+ *            longitude lam = 2 pi (x + 0.5)/W - pi,
+ *            latitude  phi = pi/2 - pi (y + 0.5)/H,
+ *            bearing   b   = (cos phi sin lam, -sin phi, cos phi cos lam)
+ *          in a frame with x right, y down, z forward.
+ * Poses:   world -> camera, X_cam = R X_world + t, R row-major, double.
+ *          Relative poses are composed in double on the host, once per
+ *          keyframe pair, and rounded to float for the kernels.
+ * Planes:  per pixel, depth = range along the unit ray in metres (0 marks
+ *          an invalid pixel), normal = unit vector in the reference camera
+ *          frame facing the camera (0 when invalid), cost = aggregated
+ *          1 - NCC in [0, 2] (2 when invalid). Each is a separate float32
+ *          H x W plane with its own pitch in elements.
+ * Valid pixels: rows r <= y <= H-1-r for patch radius r; every column (the
+ *          longitude wraps around the seam). Other rows are written invalid.
+ * Pointers: image, plane and output pointers are DEVICE pointers the caller
+ *          owns (e.g. from PyTorch); pose and parameter structs are HOST
+ *          memory read before the call returns. Inputs must stay alive until
+ *          the stream reaches the enqueued work.
+ * Streams: `stream` is a hipStream_t (0 = the null stream). Every call only
+ *          enqueues work on it and returns; the caller synchronises.
+ * Errors:  every call validates all arguments on the host before it enqueues
+ *          anything; on any error nothing is written. PMS_ERR_DEVICE carries
+ *          the HIP error text in pms_last_error(). A context is not
+ *          thread-safe: use one per stream.
+ */
+#ifndef PMS_H
+#define PMS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PMS_OK = 0,
+    PMS_ERR_INVALID_ARG = 1,
+    PMS_ERR_OUT_OF_MEMORY = 2,
+    PMS_ERR_DEVICE = 3,
+    PMS_ERR_UNSUPPORTED = 4,
+    PMS_ERR_BUDGET = 5
+} pms_status;
+
+typedef enum { PMS_F32 = 0, PMS_F16 = 1, PMS_U8 = 2 } pms_dtype;
+
+#define PMS_MAX_VIEWS 8      /* neighbours per call                        */
+#define PMS_MAX_MAPS 8       /* consistency depth maps per call            */
+#define PMS_MAX_OFFSETS 16   /* propagation neighbourhood                  */
+#define PMS_MAX_SAMPLES 64   /* samples per patch                          */
+#define PMS_MAX_TRIALS 16    /* refinement trials per pixel and sweep      */
+
+typedef struct {
+    const void *data;    /* device pointer                                 */
+    int32_t width;       /* W == 2 * height                                */
+    int32_t height;
+    int64_t pitch_bytes; /* >= width * element size                        */
+    int32_t dtype;       /* pms_dtype                                      */
+} pms_image;
+
+typedef struct {
+    float *data;         /* device pointer to an H x W float32 plane       */
+    int64_t pitch_elems; /* >= W                                           */
+} pms_plane;
+
+typedef struct {
+    double R[9]; /* world -> camera rotation, row-major                    */
+    double t[3]; /* world -> camera translation                            */
+} pms_pose;
+
+typedef struct {
+    int32_t patch_size;    /* odd >= 3; patch radius r = (patch_size-1)/2   */
+    int32_t patch_stride;  /* s >= 1 dividing 2r; samples at -r, -r+s, ..., r
+                              in x and y (row-major), at most 64 samples   */
+    int32_t iterations;    /* red + black sweeps                            */
+    int32_t refine_trials; /* random refinement trials per pixel per sweep */
+    double depth_min;      /* 0 < depth_min < depth_max, metres            */
+    double depth_max;
+    int32_t top_k;         /* views averaged; 0 => ceil(N/2)                */
+    double ncc_var_floor;  /* a view whose patch variance is below this is
+                              invalid (cost 2)                              */
+    double refine_sigma_logdepth0; /* <= 0 => 0.5 ln(depth_max/depth_min)   */
+    double refine_depth_shrink;    /* log-depth half-width factor per trial */
+    double refine_sigma_normal0;   /* normal perturbation half-width        */
+    double refine_normal_shrink;   /* its factor per trial                  */
+    int32_t n_offsets;             /* propagation neighbours, table order  */
+    int32_t offsets[PMS_MAX_OFFSETS][2]; /* (dx, dy) with odd |dx| + |dy|  */
+    double geo_px;        /* consistency: reprojection error bound, pixels */
+    double geo_rel_depth; /* consistency: relative range error bound       */
+    int32_t geo_min_views; /* maps that must agree; 0 => min(2, #maps)     */
+    uint64_t seed;        /* key of the counter-based RNG                   */
+} pms_params;
+
+typedef struct pms_context pms_context;
+
+/* Defaults: 11x11 patch sampled every 2nd pixel, 8 iterations, 6 refinement
+   trials (Sec. III-C, item 1), 0.3-30 m, the 8-neighbourhood of Sec. III-C
+   with its inner ring moved out to distance 3 and the outer ring at 5, 1 px /
+   1% consistency. Never fails for a non-null pointer. */
+pms_status pms_default_params(pms_params *out);
+
+/* Creates a context on HIP device `device`. The context owns only scratch
+   memory (plane state, reference patch statistics, bearing tables), sized on
+   first use and never above scratch_budget_bytes (0 = no limit). device == -1
+   makes a validation-only context: every call checks its arguments as usual
+   and then returns PMS_ERR_DEVICE instead of launching (no GPU needed). */
+pms_status pms_context_create(int32_t device, size_t scratch_budget_bytes, pms_context **out);
+pms_status pms_context_destroy(pms_context *ctx);
+
+/* Densifies one reference keyframe (Sec. III and III-B/C):
+   random initialisation, `iterations` red-black sweeps of propagation and
+   random refinement scored by the plane-induced warp and NCC against
+   n_nbrs neighbours, and -- when n_maps > 0 -- the geometric-consistency
+   filter against the depth maps of n_maps other keyframes (maps[k] is a
+   W x H plane of ranges, 0 = no depth, for the camera at map_poses[k]).
+   Writes depth_out, normal_out[0..2] (nx, ny, nz) and cost_out. */
+pms_status pms_densify(pms_context *ctx, const pms_image *ref, const pms_pose *ref_pose,
+                       const pms_image *nbrs, const pms_pose *nbr_poses, int32_t n_nbrs,
+                       const pms_plane *maps, const pms_pose *map_poses, int32_t n_maps,
+                       const pms_params *params, pms_plane depth_out,
+                       const pms_plane normal_out[3], pms_plane cost_out, void *stream);
+
+/* The matching cost alone (Sec. III-C: rectangular reference patch, any
+   shape in the neighbours) for caller-given hypotheses: cost_out receives the
+   aggregated cost at every pixel (2 where the pixel is invalid or depth <= 0);
+   per_view_out, if non-null, points to n_nbrs planes of per-view costs. */
+pms_status pms_eval_cost(pms_context *ctx, const pms_image *ref, const pms_pose *ref_pose,
+                         const pms_image *nbrs, const pms_pose *nbr_poses, int32_t n_nbrs,
+                         const pms_params *params, pms_plane depth_in,
+                         const pms_plane normal_in[3], pms_plane cost_out,
+                         const pms_plane *per_view_out, void *stream);
+
+/* One half-sweep of Sec. III-C (propagation from the opposite colour, then
+   random refinement) on a caller-held state: colour 0 updates pixels with
+   even x + y, colour 1 odd; `iteration` (>= 1) keys the refinement draws.
+   The state planes are read and written in place. */
+pms_status pms_halfsweep(pms_context *ctx, const pms_image *ref, const pms_pose *ref_pose,
+                         const pms_image *nbrs, const pms_pose *nbr_poses, int32_t n_nbrs,
+                         const pms_params *params, int32_t iteration, int32_t colour,
+                         pms_plane depth_io, const pms_plane normal_io[3], pms_plane cost_io,
+                         void *stream);
+
+/* The geometric-consistency filter alone (Sec. III: applied once five depth
+   maps are available) on a caller-held W x H result, in place. */
+pms_status pms_consistency(pms_context *ctx, int32_t width, int32_t height,
+                           const pms_pose *ref_pose, const pms_plane *maps,
+                           const pms_pose *map_poses, int32_t n_maps, const pms_params *params,
+                           pms_plane depth_io, const pms_plane normal_io[3], pms_plane cost_io,
+                           void *stream);
+
+/* Philox4x64-10 blocks for counters (ctr0 + i, 0, 0, 0), i < n, with key
+   (key0, key1), written to the device buffer out[4n] -- the generator the
+   kernels draw hypotheses from, exposed for testing. */
+pms_status pms_philox_stream(pms_context *ctx, uint64_t key0, uint64_t key1, uint64_t ctr0,
+                             int64_t n, uint64_t *out, void *stream);
+
+/* Per-kernel timing with HIP events around each launch (off by default).
+   pms_profile_read synchronises on the recorded events, returns the launch
+   count and total milliseconds of kernel `name` ("halfsweep", "init",
+   "refstats", "finalize", "consistency", "eval") since the last read, and
+   clears them. */
+pms_status pms_profile_enable(pms_context *ctx, int32_t on);
+pms_status pms_profile_read(pms_context *ctx, const char *name, int64_t *launches,
+                            double *total_ms);
+
+const char *pms_status_string(pms_status s);
+/* Text of the last error on this context ("" if none); valid until the next
+   call on the context. */
+const char *pms_last_error(const pms_context *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -104,6 +104,10 @@ def lib() -> C.CDLL:
                                      C.POINTER(Pose), C.POINTER(Pose), C.POINTER(Params),
                                      _D, _D, C.c_int, C.POINTER(_D), C.POINTER(Pose),
                                      _D, _D, _D, C.c_int, C.c_uint64]
+        L.pmsref_halfsweep_rows.argtypes = [C.c_int, C.c_int, _D, C.c_int, C.POINTER(_D),
+                                            C.POINTER(Pose), C.POINTER(Pose), C.POINTER(Params),
+                                            _D, _D, _D, C.c_int, C.c_int, C.c_int, C.c_int,
+                                            _D, _D, _D, C.c_int]
         L.pmsref_pixel_valid.argtypes = [C.c_int, C.c_int, C.POINTER(Params), C.c_int, C.c_int]
         _lib = L
     return _lib
@@ -309,6 +313,28 @@ def update_pixel(ref, nbrs, ref_pose, nbr_poses, params: dict, depth, normal, co
     if rc:
         raise ValueError(f"pmsref_update_pixel failed: {rc}")
     return d.value, n, c.value
+
+
+def halfsweep_rows(ref, nbrs, ref_pose, nbr_poses, params: dict, depth, normal, cost,
+                   iteration: int, colour: int, y0: int, y1: int, n_threads: int = 0):
+    """One half-sweep over rows [y0, y1); returns the new (depth, normal, cost)."""
+    ref = _f64(ref)
+    H, W = ref.shape
+    V = _Views(nbrs)
+    depth = _f64(depth)
+    normal = _f64(normal)
+    cost = _f64(cost)
+    d1 = np.empty_like(depth)
+    n1 = np.empty_like(normal)
+    c1 = np.empty_like(cost)
+    rc = lib().pmsref_halfsweep_rows(W, H, _dptr(ref), len(V.arrs), V.ptrs, _poses([ref_pose]),
+                                     _poses(nbr_poses), C.byref(make_params(params)),
+                                     _dptr(depth), _dptr(normal), _dptr(cost), int(iteration),
+                                     int(colour), int(y0), int(y1), _dptr(d1), _dptr(n1),
+                                     _dptr(c1), int(n_threads))
+    if rc:
+        raise ValueError(f"pmsref_halfsweep_rows failed: {rc}")
+    return d1, n1, c1
 
 
 def consistency(depth, normal, cost, ref_pose, maps, map_poses, params: dict,

@@ -779,6 +779,54 @@ static void sweep_range(void *vctx, long begin, long end)
     }
 }
 
+int pmsref_halfsweep_rows(int W, int H, const double *ref, int n_views, const double *const *nbrs,
+                          const pmsref_pose *ref_pose, const pmsref_pose *nbr_poses,
+                          const pmsref_params *p, const double *depth, const double *normal,
+                          const double *cost, int iteration, int colour, int y0, int y1,
+                          double *depth_out, double *normal_out, double *cost_out, int n_threads)
+{
+    int rc = pmsref_check_params(p, W, H, n_views);
+    if (rc) return rc;
+    if (n_views < 1 || (colour != 0 && colour != 1) || y0 < 0 || y1 > H || y0 > y1) return -1;
+    long HW = (long)W * H;
+    job_t J;
+    job_init(&J, W, H, ref, n_views, nbrs, ref_pose, nbr_poses, p);
+    memcpy(depth_out, depth, sizeof(double) * (size_t)HW);
+    memcpy(normal_out, normal, sizeof(double) * 3 * (size_t)HW);
+    memcpy(cost_out, cost, sizeof(double) * (size_t)HW);
+    long cap = (long)(y1 - y0) * W / 2 + 1;
+    long *pix = (long *)malloc(sizeof(long) * (size_t)cap);
+    double *nd = (double *)malloc(sizeof(double) * (size_t)cap);
+    double *nn = (double *)malloc(sizeof(double) * 3 * (size_t)cap);
+    double *nc = (double *)malloc(sizeof(double) * (size_t)cap);
+    if (!pix || !nd || !nn || !nc) {
+        free(pix);
+        free(nd);
+        free(nn);
+        free(nc);
+        return -20;
+    }
+    long np = 0;
+    for (int y = y0; y < y1; ++y)
+        for (int x = 0; x < W; ++x)
+            if (((x + y) & 1) == colour && pmsref_pixel_valid(W, H, p, x, y)) pix[np++] = (long)y * W + x;
+    sweep_ctx S = {&J, depth, normal, cost, pix, iteration, nd, nn, nc};
+    parallel_for(np, n_threads, sweep_range, &S);
+    for (long k = 0; k < np; ++k) {
+        long i = pix[k];
+        depth_out[i] = nd[k];
+        normal_out[i] = nn[3 * k];
+        normal_out[HW + i] = nn[3 * k + 1];
+        normal_out[2 * HW + i] = nn[3 * k + 2];
+        cost_out[i] = nc[k];
+    }
+    free(pix);
+    free(nd);
+    free(nn);
+    free(nc);
+    return 0;
+}
+
 static uint64_t splitmix64(uint64_t *s)
 {
     uint64_t z = (*s += 0x9E3779B97F4A7C15ULL);

@@ -127,6 +127,17 @@ int pmsref_update_pixel(int W, int H, const double *ref, int n_views,
                         const double *cost, int iteration, int x, int y,
                         double *d_out, double n_out[3], double *cost_out);
 
+/* One half-sweep (colour 0: even x+y, 1: odd) restricted to rows [y0, y1):
+   the listed pixels' updates go to the *_out arrays, every other pixel is
+   copied from the input state. */
+int pmsref_halfsweep_rows(int W, int H, const double *ref, int n_views,
+                          const double *const *nbrs, const pmsref_pose *ref_pose,
+                          const pmsref_pose *nbr_poses, const pmsref_params *p,
+                          const double *depth, const double *normal,
+                          const double *cost, int iteration, int colour, int y0,
+                          int y1, double *depth_out, double *normal_out,
+                          double *cost_out, int n_threads);
+
 /* --- geometric consistency ------------------------------------------------
    Filters (depth, normal, cost) of the reference in place against n_maps
    depth maps of other keyframes. If err_px/err_depth/agree are non-null they

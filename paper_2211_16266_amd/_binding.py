@@ -1,0 +1,323 @@
+"""Thin ctypes binding of libpms (include/pms.h) over PyTorch device tensors.
+
+Argument marshalling only: every step of the densifier runs in the HIP
+kernels of libpms. Tensors supply device memory, torch's current stream
+supplies the hipStream_t. There is no CPU fallback: without the built
+library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libpms.so")
+
+MAX_VIEWS = 8
+MAX_MAPS = 8
+MAX_OFFSETS = 16
+
+PMS_F32, PMS_F16, PMS_U8 = 0, 1, 2
+_DTYPES = {torch.float32: (PMS_F32, 4), torch.float16: (PMS_F16, 2), torch.uint8: (PMS_U8, 1)}
+
+STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "device error",
+          4: "unsupported", 5: "scratch budget exceeded"}
+
+
+class PmsError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class Image(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("width", C.c_int32), ("height", C.c_int32),
+                ("pitch_bytes", C.c_int64), ("dtype", C.c_int32)]
+
+
+class Plane(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("pitch_elems", C.c_int64)]
+
+
+class Pose(C.Structure):
+    _fields_ = [("R", C.c_double * 9), ("t", C.c_double * 3)]
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("patch_size", C.c_int32), ("patch_stride", C.c_int32), ("iterations", C.c_int32),
+        ("refine_trials", C.c_int32), ("depth_min", C.c_double), ("depth_max", C.c_double),
+        ("top_k", C.c_int32), ("ncc_var_floor", C.c_double),
+        ("refine_sigma_logdepth0", C.c_double), ("refine_depth_shrink", C.c_double),
+        ("refine_sigma_normal0", C.c_double), ("refine_normal_shrink", C.c_double),
+        ("n_offsets", C.c_int32), ("offsets", (C.c_int32 * 2) * MAX_OFFSETS),
+        ("geo_px", C.c_double), ("geo_rel_depth", C.c_double), ("geo_min_views", C.c_int32),
+        ("seed", C.c_uint64),
+    ]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """The loaded libpms; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                               "(the densifier has no CPU path)")
+        L = C.CDLL(LIB_PATH)
+        P = C.POINTER
+        L.pms_default_params.argtypes = [P(Params)]
+        L.pms_context_create.argtypes = [C.c_int32, C.c_size_t, P(C.c_void_p)]
+        L.pms_context_destroy.argtypes = [C.c_void_p]
+        L.pms_densify.argtypes = [C.c_void_p, P(Image), P(Pose), P(Image), P(Pose), C.c_int32,
+                                  P(Plane), P(Pose), C.c_int32, P(Params), Plane, P(Plane), Plane,
+                                  C.c_void_p]
+        L.pms_eval_cost.argtypes = [C.c_void_p, P(Image), P(Pose), P(Image), P(Pose), C.c_int32,
+                                    P(Params), Plane, P(Plane), Plane, P(Plane), C.c_void_p]
+        L.pms_halfsweep.argtypes = [C.c_void_p, P(Image), P(Pose), P(Image), P(Pose), C.c_int32,
+                                    P(Params), C.c_int32, C.c_int32, Plane, P(Plane), Plane,
+                                    C.c_void_p]
+        L.pms_consistency.argtypes = [C.c_void_p, C.c_int32, C.c_int32, P(Pose), P(Plane), P(Pose),
+                                      C.c_int32, P(Params), Plane, P(Plane), Plane, C.c_void_p]
+        L.pms_philox_stream.argtypes = [C.c_void_p, C.c_uint64, C.c_uint64, C.c_uint64, C.c_int64,
+                                        C.c_void_p, C.c_void_p]
+        L.pms_profile_enable.argtypes = [C.c_void_p, C.c_int32]
+        L.pms_profile_read.argtypes = [C.c_void_p, C.c_char_p, P(C.c_int64), P(C.c_double)]
+        L.pms_status_string.argtypes = [C.c_int]
+        L.pms_status_string.restype = C.c_char_p
+        L.pms_last_error.argtypes = [C.c_void_p]
+        L.pms_last_error.restype = C.c_char_p
+        for name in ("pms_default_params", "pms_context_create", "pms_context_destroy",
+                     "pms_densify", "pms_eval_cost", "pms_halfsweep", "pms_consistency",
+                     "pms_philox_stream", "pms_profile_enable", "pms_profile_read"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+# ----------------------------------------------------------------------------
+# marshalling
+# ----------------------------------------------------------------------------
+
+def default_params() -> dict:
+    p = Params()
+    lib().pms_default_params(C.byref(p))
+    d = {}
+    for name, _ in Params._fields_:
+        v = getattr(p, name)
+        if name == "offsets":
+            v = [(int(v[k][0]), int(v[k][1])) for k in range(p.n_offsets)]
+        d[name] = v
+    return d
+
+
+def make_params(overrides: dict | None = None) -> Params:
+    p = Params()
+    lib().pms_default_params(C.byref(p))
+    for k, v in (overrides or {}).items():
+        if k == "offsets":
+            if len(v) > MAX_OFFSETS:
+                raise ValueError("too many propagation offsets")
+            p.n_offsets = len(v)
+            for i, (ox, oy) in enumerate(v):
+                p.offsets[i][0] = int(ox)
+                p.offsets[i][1] = int(oy)
+        elif k != "n_offsets":
+            setattr(p, k, v)
+    return p
+
+
+def make_pose(pose) -> Pose:
+    R, t = pose
+    R = torch.as_tensor(R, dtype=torch.float64).reshape(9).tolist()
+    t = torch.as_tensor(t, dtype=torch.float64).reshape(3).tolist()
+    p = Pose()
+    for i in range(9):
+        p.R[i] = R[i]
+    for i in range(3):
+        p.t[i] = t[i]
+    return p
+
+
+def _poses(poses):
+    arr = (Pose * max(1, len(poses)))()
+    for i, pz in enumerate(poses):
+        arr[i] = make_pose(pz)
+    return arr
+
+
+def _device_2d(t: torch.Tensor, what: str) -> None:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{what} must be a device tensor")
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError(f"{what} must be 2-D with unit column stride")
+
+
+def make_image(t: torch.Tensor, what: str = "image") -> Image:
+    _device_2d(t, what)
+    if t.dtype not in _DTYPES:
+        raise ValueError(f"{what}: dtype must be float32, float16 or uint8")
+    code, size = _DTYPES[t.dtype]
+    H, W = t.shape
+    return Image(t.data_ptr(), W, H, t.stride(0) * size, code)
+
+
+def make_plane(t: torch.Tensor, what: str = "plane") -> Plane:
+    _device_2d(t, what)
+    if t.dtype != torch.float32:
+        raise ValueError(f"{what} must be float32")
+    return Plane(t.data_ptr(), t.stride(0))
+
+
+def _planes3(normal: torch.Tensor, what: str):
+    if normal.dim() != 3 or normal.shape[0] != 3:
+        raise ValueError(f"{what} must be (3, H, W)")
+    return (Plane * 3)(*[make_plane(normal[i], what) for i in range(3)])
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+class Context:
+    """A libpms context: the scratch memory of one stream's work."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 0):
+        self.device = device
+        h = C.c_void_p()
+        st = lib().pms_context_create(int(device), int(budget_bytes), C.byref(h))
+        if st:
+            raise PmsError(st, "pms_context_create")
+        self.handle = h
+
+    def check(self, st: int, what: str) -> None:
+        if st:
+            msg = lib().pms_last_error(self.handle).decode() if self.handle else ""
+            raise PmsError(st, f"{what}: {msg}")
+
+    def close(self) -> None:
+        if self.handle:
+            lib().pms_context_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def profile_enable(self, on: bool = True) -> None:
+        self.check(lib().pms_profile_enable(self.handle, int(bool(on))), "pms_profile_enable")
+
+    def profile_read(self, name: str) -> tuple[int, float]:
+        n = C.c_int64()
+        ms = C.c_double()
+        self.check(lib().pms_profile_read(self.handle, name.encode(), C.byref(n), C.byref(ms)),
+                   "pms_profile_read")
+        return n.value, ms.value
+
+
+_default_ctx: dict = {}
+
+
+def default_context(device: int = 0) -> Context:
+    if device not in _default_ctx:
+        _default_ctx[device] = Context(device)
+    return _default_ctx[device]
+
+
+def _views(nbrs):
+    if len(nbrs) > MAX_VIEWS:
+        raise ValueError("too many neighbours")
+    return (Image * max(1, len(nbrs)))(*[make_image(t, "neighbour") for t in nbrs])
+
+
+def densify(ref: torch.Tensor, nbrs, ref_pose, nbr_poses, params: dict | None = None, maps=None,
+            map_poses=None, out=None, ctx: Context | None = None, stream=None):
+    """Depth (H, W), normal (3, H, W) and cost (H, W) float32 device tensors
+    of the reference keyframe. ``maps``/``map_poses`` enable the consistency
+    filter. ``out`` may supply the three output tensors."""
+    ctx = ctx or default_context(ref.device.index or 0)
+    H, W = ref.shape
+    if out is None:
+        depth = torch.empty((H, W), dtype=torch.float32, device=ref.device)
+        normal = torch.empty((3, H, W), dtype=torch.float32, device=ref.device)
+        cost = torch.empty((H, W), dtype=torch.float32, device=ref.device)
+    else:
+        depth, normal, cost = out
+    maps = list(maps or [])
+    map_poses = list(map_poses or [])
+    if len(maps) != len(map_poses):
+        raise ValueError("maps and map_poses differ in length")
+    mp = (Plane * max(1, len(maps)))(*[make_plane(m, "map") for m in maps])
+    st = lib().pms_densify(ctx.handle, C.byref(make_image(ref, "ref")), C.byref(make_pose(ref_pose)),
+                           _views(nbrs), _poses(nbr_poses), len(nbrs),
+                           mp if maps else None, _poses(map_poses) if maps else None, len(maps),
+                           C.byref(make_params(params)), make_plane(depth, "depth"),
+                           _planes3(normal, "normal"), make_plane(cost, "cost"),
+                           C.c_void_p(_stream_handle(stream)))
+    ctx.check(st, "pms_densify")
+    return depth, normal, cost
+
+
+def eval_cost(ref: torch.Tensor, nbrs, ref_pose, nbr_poses, params: dict | None, depth: torch.Tensor,
+              normal: torch.Tensor, per_view: bool = False, ctx: Context | None = None, stream=None):
+    """Aggregated cost (H, W) of given hypotheses, and the per-view costs
+    (N, H, W) when ``per_view``."""
+    ctx = ctx or default_context(ref.device.index or 0)
+    H, W = ref.shape
+    cost = torch.empty((H, W), dtype=torch.float32, device=ref.device)
+    pv = torch.empty((len(nbrs), H, W), dtype=torch.float32, device=ref.device) if per_view else None
+    pvp = (Plane * len(nbrs))(*[make_plane(pv[j]) for j in range(len(nbrs))]) if per_view else None
+    st = lib().pms_eval_cost(ctx.handle, C.byref(make_image(ref, "ref")), C.byref(make_pose(ref_pose)),
+                             _views(nbrs), _poses(nbr_poses), len(nbrs),
+                             C.byref(make_params(params)), make_plane(depth, "depth"),
+                             _planes3(normal, "normal"), make_plane(cost, "cost"), pvp,
+                             C.c_void_p(_stream_handle(stream)))
+    ctx.check(st, "pms_eval_cost")
+    return (cost, pv) if per_view else cost
+
+
+def halfsweep(ref: torch.Tensor, nbrs, ref_pose, nbr_poses, params: dict | None, iteration: int,
+              colour: int, depth: torch.Tensor, normal: torch.Tensor, cost: torch.Tensor,
+              ctx: Context | None = None, stream=None) -> None:
+    """One red (colour 0) or black (colour 1) half-sweep on the given state,
+    in place."""
+    ctx = ctx or default_context(ref.device.index or 0)
+    st = lib().pms_halfsweep(ctx.handle, C.byref(make_image(ref, "ref")), C.byref(make_pose(ref_pose)),
+                             _views(nbrs), _poses(nbr_poses), len(nbrs),
+                             C.byref(make_params(params)), int(iteration), int(colour),
+                             make_plane(depth, "depth"), _planes3(normal, "normal"),
+                             make_plane(cost, "cost"), C.c_void_p(_stream_handle(stream)))
+    ctx.check(st, "pms_halfsweep")
+
+
+def consistency(ref_pose, maps, map_poses, params: dict | None, depth: torch.Tensor,
+                normal: torch.Tensor, cost: torch.Tensor, ctx: Context | None = None,
+                stream=None) -> None:
+    """Geometric-consistency filter of (depth, normal, cost), in place."""
+    ctx = ctx or default_context(depth.device.index or 0)
+    H, W = depth.shape
+    mp = (Plane * max(1, len(maps)))(*[make_plane(m, "map") for m in maps])
+    st = lib().pms_consistency(ctx.handle, W, H, C.byref(make_pose(ref_pose)), mp,
+                               _poses(map_poses), len(maps), C.byref(make_params(params)),
+                               make_plane(depth, "depth"), _planes3(normal, "normal"),
+                               make_plane(cost, "cost"), C.c_void_p(_stream_handle(stream)))
+    ctx.check(st, "pms_consistency")
+
+
+def philox_stream(key0: int, key1: int, ctr0: int, n: int, device: int = 0,
+                  ctx: Context | None = None, stream=None) -> torch.Tensor:
+    """(n, 4) int64 tensor holding the uint64 Philox4x64-10 blocks."""
+    ctx = ctx or default_context(device)
+    out = torch.empty((n, 4), dtype=torch.int64, device=f"cuda:{device}")
+    st = lib().pms_philox_stream(ctx.handle, int(key0), int(key1), int(ctr0), int(n),
+                                 C.c_void_p(out.data_ptr()), C.c_void_p(_stream_handle(stream)))
+    ctx.check(st, "pms_philox_stream")
+    return out

@@ -251,3 +251,21 @@ def test_cost_ties_keep_the_current_plane():
     assert np.all(a[2][3:H - 3] == 2.0)
     for u, v in zip(a, b):
         assert np.array_equal(u, v)
+
+
+def test_row_band_halfsweeps_compose_to_a_full_iteration():
+    w = synth.scaled("box_room", 96, seed=4)
+    imgs = w.images_f32()
+    args = (imgs[w.ref], [imgs[i] for i in w.nbrs], w.poses[w.ref], [w.poses[i] for i in w.nbrs])
+    p0 = dict(w.params, iterations=0, seed=5)
+    p1 = dict(w.params, iterations=1, seed=5)
+    d, n, c = oracle.densify(*args, p0)
+    for colour in (0, 1):
+        # two bands, each updated from the same input state
+        da, na, ca = oracle.halfsweep_rows(*args, p1, d, n, c, 1, colour, 0, 20)
+        db, nb, cb = oracle.halfsweep_rows(*args, p1, d, n, c, 1, colour, 20, w.H)
+        d = np.where(np.arange(w.H)[:, None] < 20, da, db)
+        n = np.where(np.arange(w.H)[None, :, None] < 20, na, nb)
+        c = np.where(np.arange(w.H)[:, None] < 20, ca, cb)
+    e = oracle.densify(*args, p1)
+    assert np.array_equal(d, e[0]) and np.array_equal(n, e[1]) and np.array_equal(c, e[2])
