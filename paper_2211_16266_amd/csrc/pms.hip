@@ -41,7 +41,12 @@ struct pms_context {
     float2 *stats = nullptr;
     float2 *tab_row = nullptr;
     float2 *tab_col = nullptr;
+    double2 *tab_row64 = nullptr;
+    double2 *tab_col64 = nullptr;
     int tab_W = 0, tab_H = 0;
+    void *pad[pms::MAXV] = {};  // re-laid-out neighbour images
+    int pad_Wp = 0;
+    int pad_bytes = 0;
     std::string last_error;
     bool profiling = false;
     std::vector<TimedLaunch> launches;
@@ -203,8 +208,22 @@ bool check_ref_and_views(pms_context *ctx, const pms_image *ref, const pms_pose 
     return true;
 }
 
-// X_nbr = (R_n R_r^T) X_ref + (t_n - R_n R_r^T t_r), composed in FP64 and
-// rounded once to float.
+// X_nbr = (R_n R_r^T) X_ref + (t_n - R_n R_r^T t_r), composed in FP64.
+pms::ViewPoseD relative_pose64(const pms_pose &ref, const pms_pose &nbr)
+{
+    pms::ViewPoseD out;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < 3; ++k) s += nbr.R[3 * i + k] * ref.R[3 * j + k];
+            out.R[3 * i + j] = s;
+        }
+    for (int i = 0; i < 3; ++i)
+        out.t[i] = nbr.t[i] - (out.R[3 * i] * ref.t[0] + out.R[3 * i + 1] * ref.t[1] + out.R[3 * i + 2] * ref.t[2]);
+    return out;
+}
+
+// The same, rounded once to float (consistency filter).
 pms::ViewPoseF relative_pose(const pms_pose &ref, const pms_pose &nbr)
 {
     double R[9], t[3];
@@ -221,16 +240,23 @@ pms::ViewPoseF relative_pose(const pms_pose &ref, const pms_pose &nbr)
     return out;
 }
 
-// Grows the scratch block to hold W x H pixels and the bearing tables.
-pms_status ensure_scratch(pms_context *ctx, int W, int H, hipStream_t stream)
+size_t pad_elem_size(int dtype) { return dtype == PMS_F16 ? 2 : 4; }
+
+// Grows the scratch block to hold W x H pixels of state, the bearing tables
+// and n_pad re-laid-out neighbour images of `pad_elem` bytes per value.
+pms_status ensure_scratch(pms_context *ctx, int W, int H, int n_pad, size_t pad_elem,
+                          hipStream_t stream)
 {
     const long long npx = (long long)W * H;
     const size_t state_b = (size_t)npx * sizeof(float4);
     const size_t cost_b = (size_t)npx * sizeof(float);
     const size_t stats_b = (size_t)npx * sizeof(float2);
-    const size_t tabs_b = (size_t)(W + H) * sizeof(float2);
+    const size_t tabs_b = (size_t)(W + H) * (sizeof(float2) + sizeof(double2));
+    const int Wp = 2 * W + 4;
+    const size_t pad_b = (size_t)(H + 2) * Wp * pad_elem;
     auto align = [](size_t v) { return (v + 255) & ~(size_t)255; };
-    const size_t need = align(state_b) + align(cost_b) + align(stats_b) + align(tabs_b);
+    const size_t need = align(state_b) + align(cost_b) + align(stats_b) + align(tabs_b) +
+                        (size_t)n_pad * align(pad_b);
     if (ctx->device < 0) return fail(ctx, PMS_ERR_DEVICE, "validation-only context cannot launch");
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
@@ -261,12 +287,21 @@ pms_status ensure_scratch(pms_context *ctx, int W, int H, hipStream_t stream)
     ctx->stats = reinterpret_cast<float2 *>(base);
     base += align(stats_b);
     float2 *tabs = reinterpret_cast<float2 *>(base);
+    base += align(tabs_b);
+    for (int j = 0; j < pms::MAXV; ++j) {
+        ctx->pad[j] = j < n_pad ? static_cast<void *>(base) : nullptr;
+        if (j < n_pad) base += align(pad_b);
+    }
+    ctx->pad_Wp = Wp;
+    ctx->pad_bytes = (int)pad_b;
     if (ctx->tab_W != W || ctx->tab_H != H || ctx->tab_row != tabs) {
         ctx->tab_row = tabs;
         ctx->tab_col = tabs + H;
+        ctx->tab_row64 = reinterpret_cast<double2 *>(tabs + W + H);
+        ctx->tab_col64 = ctx->tab_row64 + H;
         const int n = W > H ? W : H;
         hipLaunchKernelGGL(pms::k_tables, dim3((n + 255) / 256), dim3(256), 0, stream, W, H,
-                           ctx->tab_row, ctx->tab_col);
+                           ctx->tab_row, ctx->tab_col, ctx->tab_row64, ctx->tab_col64);
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(ctx, e, "k_tables launch");
         ctx->tab_W = W;
@@ -352,12 +387,16 @@ void fill_common(pms::SweepArgs &A, const pms_context *ctx, const pms_image *ref
     A.ref.ptr = ref->data;
     A.ref.pitch = ref->pitch_bytes;
     for (int j = 0; j < n_nbrs; ++j) {
-        A.nbr[j].ptr = nbrs[j].data;
-        A.nbr[j].pitch = nbrs[j].pitch_bytes;
-        A.pose[j] = relative_pose(*ref_pose, nbr_poses[j]);
+        A.pad[j] = ctx->pad[j];
+        A.pose[j] = relative_pose64(*ref_pose, nbr_poses[j]);
+        A.posef[j] = relative_pose(*ref_pose, nbr_poses[j]);
     }
+    A.Wp = ctx->pad_Wp;
+    A.pad_bytes = ctx->pad_bytes;
     A.tab_row = ctx->tab_row;
     A.tab_col = ctx->tab_col;
+    A.tab_row64 = ctx->tab_row64;
+    A.tab_col64 = ctx->tab_col64;
     A.stats = ctx->stats;
     A.state = ctx->state;
     A.cost = ctx->cost;
@@ -374,50 +413,86 @@ dim3 tile_grid(pms::SweepArgs &A, int cols, int rows)
     return dim3(8 * A.tiles_per_xcd);
 }
 
-// Samples per lane: the smallest compiled SPL >= ceil(P / 4).
-int pick_spl(int P)
+// Samples per lane and whether every lane owns exactly that many: the
+// smallest compiled variant for P samples over 4 lanes.
+void pick_variant(int P, int *spl, bool *full)
 {
     const int need = (P + pms::LPP - 1) / pms::LPP;
-    if (need <= 4) return 4;
-    if (need <= 9) return 9;
-    if (need <= 13) return 13;
-    return 16;
+    const bool even = P % pms::LPP == 0;
+    if (even && (need == 9 || need == 16)) {
+        *spl = need;
+        *full = true;
+        return;
+    }
+    *full = false;
+    *spl = need <= 4 ? 4 : need <= 9 ? 9 : need <= 13 ? 13 : 16;
 }
 
-template <typename T, int SPL>
+template <int DT, int SPL, bool FULL>
 void launch_kernel(int kind, const pms::SweepArgs &A, dim3 grid, hipStream_t s)
 {
     switch (kind) {
-    case KK_INIT: hipLaunchKernelGGL((pms::k_init<T, SPL>), grid, dim3(pms::BLOCK), 0, s, A); break;
-    case KK_HALFSWEEP: hipLaunchKernelGGL((pms::k_halfsweep<T, SPL>), grid, dim3(pms::BLOCK), 0, s, A); break;
-    case KK_EVAL: hipLaunchKernelGGL((pms::k_eval<T, SPL>), grid, dim3(pms::BLOCK), 0, s, A); break;
+    case KK_INIT: hipLaunchKernelGGL((pms::k_init<DT, SPL, FULL>), grid, dim3(pms::BLOCK), 0, s, A); break;
+    case KK_HALFSWEEP: hipLaunchKernelGGL((pms::k_halfsweep<DT, SPL, FULL>), grid, dim3(pms::BLOCK), 0, s, A); break;
+    case KK_EVAL: hipLaunchKernelGGL((pms::k_eval<DT, SPL, FULL>), grid, dim3(pms::BLOCK), 0, s, A); break;
     default: break;
     }
 }
 
-template <typename T>
-void launch_spl(int kind, int spl, const pms::SweepArgs &A, dim3 grid, hipStream_t s)
+template <int DT>
+void launch_variant(int kind, int spl, bool full, const pms::SweepArgs &A, dim3 grid, hipStream_t s)
 {
-    switch (spl) {
-    case 4: launch_kernel<T, 4>(kind, A, grid, s); break;
-    case 9: launch_kernel<T, 9>(kind, A, grid, s); break;
-    case 13: launch_kernel<T, 13>(kind, A, grid, s); break;
-    default: launch_kernel<T, 16>(kind, A, grid, s); break;
-    }
+    if (full && spl == 9) launch_kernel<DT, 9, true>(kind, A, grid, s);
+    else if (full && spl == 16) launch_kernel<DT, 16, true>(kind, A, grid, s);
+    else if (spl == 4) launch_kernel<DT, 4, false>(kind, A, grid, s);
+    else if (spl == 9) launch_kernel<DT, 9, false>(kind, A, grid, s);
+    else if (spl == 13) launch_kernel<DT, 13, false>(kind, A, grid, s);
+    else launch_kernel<DT, 16, false>(kind, A, grid, s);
 }
 
 pms_status launch(pms_context *ctx, int kind, int dtype, const pms::SweepArgs &A, dim3 grid,
                   hipStream_t s)
 {
     LaunchTimer timer(ctx, kind, s);
-    const int spl = pick_spl(A.P);
+    int spl;
+    bool full;
+    pick_variant(A.P, &spl, &full);
     switch (dtype) {
-    case PMS_F32: launch_spl<float>(kind, spl, A, grid, s); break;
-    case PMS_F16: launch_spl<__half>(kind, spl, A, grid, s); break;
-    default: launch_spl<uint8_t>(kind, spl, A, grid, s); break;
+    case PMS_F32: launch_variant<pms::DT_F32>(kind, spl, full, A, grid, s); break;
+    case PMS_F16: launch_variant<pms::DT_F16>(kind, spl, full, A, grid, s); break;
+    default: launch_variant<pms::DT_U8>(kind, spl, full, A, grid, s); break;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(ctx, e, kKernelNames[kind]);
+    return PMS_OK;
+}
+
+// Re-lays out the neighbour images into the context's scratch.
+pms_status launch_pad(pms_context *ctx, const pms_image *nbrs, int n_nbrs, hipStream_t s)
+{
+    LaunchTimer timer(ctx, KK_IO, s);
+    const int W = nbrs[0].width, H = nbrs[0].height, Wp = ctx->pad_Wp;
+    const long long n = (long long)(H + 2) * Wp;
+    dim3 grid((unsigned)((n + pms::BLOCK - 1) / pms::BLOCK));
+    for (int j = 0; j < n_nbrs; ++j) {
+        pms::ImgRef src{nbrs[j].data, nbrs[j].pitch_bytes};
+        switch (nbrs[j].dtype) {
+        case PMS_F32:
+            hipLaunchKernelGGL(pms::k_pad<pms::DT_F32>, grid, dim3(pms::BLOCK), 0, s, src, W, H, Wp,
+                               static_cast<float *>(ctx->pad[j]));
+            break;
+        case PMS_F16:
+            hipLaunchKernelGGL(pms::k_pad<pms::DT_F16>, grid, dim3(pms::BLOCK), 0, s, src, W, H, Wp,
+                               static_cast<__half *>(ctx->pad[j]));
+            break;
+        default:
+            hipLaunchKernelGGL(pms::k_pad<pms::DT_U8>, grid, dim3(pms::BLOCK), 0, s, src, W, H, Wp,
+                               static_cast<float *>(ctx->pad[j]));
+            break;
+        }
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(ctx, e, "pad");
     return PMS_OK;
 }
 
@@ -427,9 +502,9 @@ pms_status launch_refstats(pms_context *ctx, int dtype, const pms::SweepArgs &A,
     const long long n = (long long)A.W * A.H;
     dim3 grid((unsigned)((n + pms::BLOCK - 1) / pms::BLOCK));
     switch (dtype) {
-    case PMS_F32: hipLaunchKernelGGL(pms::k_refstats<float>, grid, dim3(pms::BLOCK), 0, s, A); break;
-    case PMS_F16: hipLaunchKernelGGL(pms::k_refstats<__half>, grid, dim3(pms::BLOCK), 0, s, A); break;
-    default: hipLaunchKernelGGL(pms::k_refstats<uint8_t>, grid, dim3(pms::BLOCK), 0, s, A); break;
+    case PMS_F32: hipLaunchKernelGGL(pms::k_refstats<pms::DT_F32>, grid, dim3(pms::BLOCK), 0, s, A); break;
+    case PMS_F16: hipLaunchKernelGGL(pms::k_refstats<pms::DT_F16>, grid, dim3(pms::BLOCK), 0, s, A); break;
+    default: hipLaunchKernelGGL(pms::k_refstats<pms::DT_U8>, grid, dim3(pms::BLOCK), 0, s, A); break;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(ctx, e, "refstats");
@@ -636,10 +711,11 @@ pms_status pms_densify(pms_context *ctx, const pms_image *ref, const pms_pose *r
     if (!check_outputs(ctx, W, depth_out, normal_out, cost_out, &st)) return st;
     if (!check_maps(ctx, maps, map_poses, n_maps, W, &st)) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if ((st = ensure_scratch(ctx, W, H, s)) != PMS_OK) return st;
+    if ((st = ensure_scratch(ctx, W, H, n_nbrs, pad_elem_size(ref->dtype), s)) != PMS_OK) return st;
 
     pms::SweepArgs A;
     fill_common(A, ctx, ref, ref_pose, nbrs, nbr_poses, n_nbrs, params);
+    if ((st = launch_pad(ctx, nbrs, n_nbrs, s)) != PMS_OK) return st;
     if ((st = launch_refstats(ctx, ref->dtype, A, s)) != PMS_OK) return st;
     dim3 g_all = tile_grid(A, W, H);
     if ((st = launch(ctx, KK_INIT, ref->dtype, A, g_all, s)) != PMS_OK) return st;
@@ -687,9 +763,10 @@ pms_status pms_eval_cost(pms_context *ctx, const pms_image *ref, const pms_pose 
         }
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if ((st = ensure_scratch(ctx, W, H, s)) != PMS_OK) return st;
+    if ((st = ensure_scratch(ctx, W, H, n_nbrs, pad_elem_size(ref->dtype), s)) != PMS_OK) return st;
     pms::SweepArgs A;
     fill_common(A, ctx, ref, ref_pose, nbrs, nbr_poses, n_nbrs, params);
+    if ((st = launch_pad(ctx, nbrs, n_nbrs, s)) != PMS_OK) return st;
     A.in_depth = depth_in.data;
     A.in_n0 = normal_in[0].data;
     A.in_n1 = normal_in[1].data;
@@ -719,9 +796,10 @@ pms_status pms_halfsweep(pms_context *ctx, const pms_image *ref, const pms_pose 
     if (iteration < 1) return fail(ctx, PMS_ERR_INVALID_ARG, "iteration must be >= 1");
     if (colour != 0 && colour != 1) return fail(ctx, PMS_ERR_INVALID_ARG, "colour must be 0 or 1");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if ((st = ensure_scratch(ctx, W, H, s)) != PMS_OK) return st;
+    if ((st = ensure_scratch(ctx, W, H, n_nbrs, pad_elem_size(ref->dtype), s)) != PMS_OK) return st;
     pms::SweepArgs A;
     fill_common(A, ctx, ref, ref_pose, nbrs, nbr_poses, n_nbrs, params);
+    if ((st = launch_pad(ctx, nbrs, n_nbrs, s)) != PMS_OK) return st;
     pms::IoArgs io = io_args(ctx, W, H, A.r, depth_io, normal_io, cost_io);
     if ((st = launch_io(ctx, 1, io, 0, s)) != PMS_OK) return st;
     if ((st = launch_refstats(ctx, ref->dtype, A, s)) != PMS_OK) return st;
@@ -753,7 +831,7 @@ pms_status pms_consistency(pms_context *ctx, int32_t width, int32_t height,
     if (!check_maps(ctx, maps, map_poses, n_maps, width, &st)) return st;
     if (!check_outputs(ctx, width, depth_io, normal_io, cost_io, &st)) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if ((st = ensure_scratch(ctx, width, height, s)) != PMS_OK) return st;
+    if ((st = ensure_scratch(ctx, width, height, 0, 4, s)) != PMS_OK) return st;
     return launch_consistency(ctx, width, height, (params->patch_size - 1) / 2, ref_pose, maps,
                               map_poses, n_maps, params, depth_io, normal_io, cost_io, s);
 }

@@ -11,14 +11,37 @@
 //     (red-black sweep) or of all pixels (init / cost evaluation); tiles are
 //     handed out so that each XCD walks a contiguous band of rows and keeps
 //     the matching part of the neighbour images in its own L2.
-//   * Everything is FP32 except the bearing tables, which are computed in
-//     FP64 once per image size and rounded.
+//   * Neighbour images are re-laid out once per call: every row is repeated
+//     around the seam to width 2W + 4 (columns -W/2-2 .. 3W/2+1), and the
+//     first and last rows are repeated once more above and below (the
+//     clamped pole taps). Any warped sample then reads its two bilinear rows
+//     as two 8-byte buffer loads at an offset built by one add and one clamp
+//     per axis, with no seam or pole test; buffer loads carry the image size,
+//     so no address can leave the image.
+//   * Precision split: what is shared by all samples of one (pixel,
+//     hypothesis, view) -- relative pose, plane homography, anchor rotation,
+//     warped centre ray and its latitude offset -- is formed in FP64 (on
+//     MI355X an FP64 FMA issues at the FP32 rate); each sample then works in
+//     FP32 on small quantities only: its bearing minus the centre bearing
+//     (formed in FP64 at set-up), the homography applied to that difference,
+//     and local angles. A shared rounding would shift the whole patch
+//     coherently, which NCC feels most; per-sample roundings of small
+//     offsets do not.
 //
-// The warp of a sample is written in homography form: with the plane
-// {X : n.X = c}, c = d (n.b_p) < 0, the neighbour ray of sample bearing b_q is
-// proportional to H b_q, H = R + t n^T / c, with a positive factor whenever
-// the plane lies in front of the sample ray (n.b_q < 0), so the projected
-// pixel equals that of R X_q + t with X_q = (c / n.b_q) b_q.
+// Warp. With the plane {X : n.X = c}, c = d (n.b_p) < 0, the neighbour ray of
+// sample bearing b_q is a positive multiple of M b_q, M = (-c) R - t n^T,
+// whenever the plane lies in front of the sample ray (n.b_q < 0); its pixel
+// equals that of R X_q + t with X_q = (c / n.b_q) b_q.
+//
+// Anchored coordinates. A pixel coordinate near 1920 carries only ~1e-4 px
+// in FP32, which is felt by NCC at the 1e-4 level. Each (pixel, hypothesis,
+// view) therefore picks an anchor pixel (U0, V0) next to the warped patch
+// centre: M is turned about the vertical by the anchor column's longitude, so
+// a sample's longitude offset is atan2 of the turned ray, and its latitude
+// offset from the anchor row is atan2 of sin/cos of the difference, which is
+// the centre's (FP64) plus a small per-sample increment. The offsets are
+// small and carry FP32 relative precision; only integers are added to the
+// anchor.
 #pragma once
 
 #include <hip/hip_fp16.h>
@@ -33,10 +56,20 @@ constexpr int MAXOFF = 16;    // propagation offsets
 constexpr int MAXTRIAL = 16;  // refinement trials
 constexpr int TILE = 8;       // 8x8 pixel tile per 256-thread workgroup
 constexpr int BLOCK = 256;
+// Re-laid-out neighbour image: H + 2 rows of 2W + 4 values;
+// logical column x is stored at x + W/2 + 2, logical row y at y + 1.
+
+// dtype codes of the C ABI
+constexpr int DT_F32 = 0, DT_F16 = 1, DT_U8 = 2;
 
 struct ViewPoseF {
     float R[9];
     float t[3];
+};
+
+struct ViewPoseD {
+    double R[9];
+    double t[3];
 };
 
 struct ImgRef {
@@ -61,20 +94,43 @@ struct SweepArgs {
     int iteration, colour;
     int tiles_x, tiles_y, tiles_per_xcd;
     ImgRef ref;
-    ImgRef nbr[MAXV];
-    ViewPoseF pose[MAXV];
+    ViewPoseD pose[MAXV];    // relative poses in FP64 (warped centre ray)
+    ViewPoseF posef[MAXV];   // the same rounded (homography on offsets)
+    const void *pad[MAXV];  // re-laid-out neighbours, (H + 2) x Wp elements
+    int Wp;                 // their pitch in elements, 2W + 4
+    int pad_bytes;          // bytes of one re-laid-out image
     const float2 *tab_row;  // per row (sin phi, cos phi)
     const float2 *tab_col;  // per column (sin lam, cos lam)
+    const double2 *tab_row64;
+    const double2 *tab_col64;
     const float2 *stats;    // per pixel (mean, variance) of the reference patch
     float4 *state;          // per pixel (nx, ny, nz, depth)
     float *cost;            // per pixel aggregated cost
-    // caller planes (eval: inputs/outputs; halfsweep io packing)
+    // caller planes (eval)
     const float *in_depth;
     const float *in_n0, *in_n1, *in_n2;
     long long in_pitch;
     float *out_cost;
     long long out_pitch;
     float *view_out[MAXV];
+};
+
+template <int DT>
+struct Storage;
+template <>
+struct Storage<DT_F32> {
+    using ref_t = float;
+    using pad_t = float;
+};
+template <>
+struct Storage<DT_F16> {
+    using ref_t = __half;
+    using pad_t = __half;
+};
+template <>
+struct Storage<DT_U8> {
+    using ref_t = uint8_t;
+    using pad_t = float;  // 8-bit neighbours are widened (and scaled) once
 };
 
 // ---------------------------------------------------------------------------
@@ -119,27 +175,27 @@ __device__ __forceinline__ float load_px<uint8_t>(const ImgRef &im, int x, int y
     return (float)(static_cast<const uint8_t *>(im.ptr) + (long long)y * im.pitch)[x] * (1.0f / 255.0f);
 }
 
-// Bilinear sample; longitude wraps around the seam, latitude taps clamp to
-// the first/last row. Coordinates are clamped to the image first, which also
-// maps NaN to the border, so every tap is in bounds.
-template <typename T>
-__device__ __forceinline__ float bilinear(const ImgRef &im, int W, int H, float u, float v)
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, int bytes)
 {
-    u = fminf(fmaxf(u, -0.5f), (float)W - 0.5f);
-    v = fminf(fmaxf(v, -0.5f), (float)H - 0.5f);
-    float fu = floorf(u), fv = floorf(v);
-    float au = u - fu, av = v - fv;
-    int x0 = (int)fu, y0 = (int)fv;
-    int x1 = x0 + 1, y1 = y0 + 1;
-    x0 = x0 < 0 ? W - 1 : x0;
-    x1 = x1 >= W ? 0 : x1;
-    y0 = y0 < 0 ? 0 : y0;
-    y1 = y1 > H - 1 ? H - 1 : y1;
-    float p00 = load_px<T>(im, x0, y0), p01 = load_px<T>(im, x1, y0);
-    float p10 = load_px<T>(im, x0, y1), p11 = load_px<T>(im, x1, y1);
-    float top = fmaf(au, p01 - p00, p00);
-    float bot = fmaf(au, p11 - p10, p10);
-    return fmaf(av, bot - top, top);
+    // raw buffer (stride 0), gfx9 descriptor word 3
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, bytes, 0x00020000);
+}
+
+// Two horizontally adjacent values of a re-laid-out image at a byte offset.
+template <typename P>
+__device__ __forceinline__ float2 load_pair(__amdgpu_buffer_rsrc_t r, int byte_off);
+
+template <>
+__device__ __forceinline__ float2 load_pair<float>(__amdgpu_buffer_rsrc_t r, int byte_off)
+{
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0));
+}
+
+template <>
+__device__ __forceinline__ float2 load_pair<__half>(__amdgpu_buffer_rsrc_t r, int byte_off)
+{
+    const __half2 h = __builtin_bit_cast(__half2, __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
+    return __half22float2(h);
 }
 
 __device__ __forceinline__ void bearing(const SweepArgs &A, int x, int y, float b[3])
@@ -148,6 +204,29 @@ __device__ __forceinline__ void bearing(const SweepArgs &A, int x, int y, float 
     b[0] = rw.y * cl.x;
     b[1] = -rw.x;
     b[2] = rw.y * cl.y;
+}
+
+// atan2 for the sample coordinates: octant reduction to t in [0, 1] and
+// atan(t) = t + t s P(s), s = t^2, with a degree-6 P fitted for minimum
+// relative error (3.5e-7 when evaluated in FP32; fitted by atan_coeffs.py).
+// Both arguments zero give 0.
+__device__ __forceinline__ float atan2_local(float y, float x)
+{
+    const float ax = fabsf(x), ay = fabsf(y);
+    const float mx = fmaxf(fmaxf(ax, ay), 1e-30f);
+    const float mn = fminf(ax, ay);
+    const float t = mn * __builtin_amdgcn_rcpf(mx);
+    const float s = t * t;
+    float p = fmaf(s, -4.582961090e-03f, 2.390408702e-02f);
+    p = fmaf(p, s, -5.909144133e-02f);
+    p = fmaf(p, s, 9.897302091e-02f);
+    p = fmaf(p, s, -1.402012706e-01f);
+    p = fmaf(p, s, 1.997216046e-01f);
+    p = fmaf(p, s, -3.333249390e-01f);
+    float r = fmaf(t * s, p, t);
+    r = ay > ax ? 1.57079632679489662f - r : r;
+    r = x < 0.0f ? 3.14159265358979324f - r : r;
+    return copysignf(r, y);
 }
 
 // Philox4x64-10 (Salmon et al., SC'11), counter (c0, c1, c2, c3), key (k0, k1).
@@ -186,37 +265,49 @@ __device__ __forceinline__ void uniforms(unsigned long long seed, unsigned long 
 
 template <int SPL>
 struct Patch {
-    float b[SPL][3];  // sample bearings
-    float rc[SPL];    // reference samples minus the patch mean
-    int nmine;        // samples owned by this lane (<= SPL)
-    float bp[3];      // bearing of the pixel itself
+    float b[SPL][3];  // sample bearing minus the pixel's bearing (FP64, rounded)
+    float rc[SPL];    // reference samples minus the patch mean (0 if not owned)
+    float wt[SPL];    // 1 for a sample this lane owns, else 0
+    double bp64[3];   // bearing of the pixel itself
+    float bp[3];      // the same, rounded
     float var_r;      // reference patch variance
 };
 
-template <typename T, int SPL>
+template <typename TR, int SPL>
 __device__ __forceinline__ void patch_setup(const SweepArgs &A, int x, int y, int lane,
                                             Patch<SPL> &pt)
 {
-    bearing(A, x, y, pt.bp);
+    {
+        const double2 rw = A.tab_row64[y], cl = A.tab_col64[x];
+        pt.bp64[0] = rw.y * cl.x;
+        pt.bp64[1] = -rw.x;
+        pt.bp64[2] = rw.y * cl.y;
+        for (int a = 0; a < 3; ++a) pt.bp[a] = (float)pt.bp64[a];
+    }
     float2 st = A.stats[(long long)y * A.W + x];
     pt.var_r = st.y;
-    pt.nmine = (A.P - lane + LPP - 1) / LPP;
 #pragma unroll
     for (int i = 0; i < SPL; ++i) {
-        int q = lane + LPP * i;
+        const int q = lane + LPP * i;
         if (q < A.P) {
-            int row = q / A.side;
-            int col = q - row * A.side;
+            const int row = q / A.side;
+            const int col = q - row * A.side;
             int xq = x - A.r + col * A.stride;
             xq = xq < 0 ? xq + A.W : (xq >= A.W ? xq - A.W : xq);
-            int yq = y - A.r + row * A.stride;
-            bearing(A, xq, yq, pt.b[i]);
-            pt.rc[i] = load_px<T>(A.ref, xq, yq) - st.x;
+            const int yq = y - A.r + row * A.stride;
+            const double2 rw = A.tab_row64[yq], cl = A.tab_col64[xq];
+            pt.b[i][0] = (float)(rw.y * cl.x - pt.bp64[0]);
+            pt.b[i][1] = (float)(-rw.x - pt.bp64[1]);
+            pt.b[i][2] = (float)(rw.y * cl.y - pt.bp64[2]);
+            pt.rc[i] = load_px<TR>(A.ref, xq, yq) - st.x;
+            pt.wt[i] = 1.0f;
         } else {
-            pt.b[i][0] = pt.bp[0];
-            pt.b[i][1] = pt.bp[1];
-            pt.b[i][2] = pt.bp[2];
+            // the pixel's own ray, so that the unused slot stays finite
+            pt.b[i][0] = 0.0f;
+            pt.b[i][1] = 0.0f;
+            pt.b[i][2] = 0.0f;
             pt.rc[i] = 0.0f;
+            pt.wt[i] = 0.0f;
         }
     }
 }
@@ -224,64 +315,129 @@ __device__ __forceinline__ void patch_setup(const SweepArgs &A, int x, int y, in
 // Aggregated cost of plane (d, n) at the pixel of `pt`: per view, warp every
 // sample, bilinear-sample the neighbour, two-pass NCC, cost = 1 - NCC or 2
 // when invalid; then the mean of the top_k smallest view costs. All 4 lanes
-// of the quad return the same value. When VIEWS is set, lane 0 of the quad
-// writes each view's cost to A.view_out[j][out_index].
-template <typename T, int SPL, bool VIEWS>
+// of the quad return the same value. FULL: every lane owns SPL samples (P is
+// a multiple of 4), so no slot is masked. When VIEWS is set, lane 0 of the
+// quad writes each view's cost to A.view_out[j][out_index].
+template <typename PT, int SPL, bool FULL, bool VIEWS>
 __device__ __forceinline__ float evaluate(const SweepArgs &A, const Patch<SPL> &pt, float d,
                                           float n0, float n1, float n2, int lane,
                                           long long out_index)
 {
-    float c = d * (n0 * pt.bp[0] + n1 * pt.bp[1] + n2 * pt.bp[2]);
-    int ok = c < 0.0f;
+    const double n64[3] = {(double)n0, (double)n1, (double)n2};
+    const double nbp = n64[0] * pt.bp64[0] + n64[1] * pt.bp64[1] + n64[2] * pt.bp64[2];
+    const double c64 = (double)d * nbp;
+    const float nbpf = (float)nbp;
+    int ok = c64 < 0.0;
 #pragma unroll
-    for (int i = 0; i < SPL; ++i)
-        if (i < pt.nmine) ok &= (n0 * pt.b[i][0] + n1 * pt.b[i][1] + n2 * pt.b[i][2]) < 0.0f;
+    for (int i = 0; i < SPL; ++i) {
+        // n . b_q = n . b_p + n . (b_q - b_p)
+        const float den = fmaf(n0, pt.b[i][0], fmaf(n1, pt.b[i][1], fmaf(n2, pt.b[i][2], nbpf)));
+        ok &= FULL ? (den < 0.0f) : (den < 0.0f || pt.wt[i] == 0.0f);
+    }
     ok = quad_and(ok);
     if (!ok) {
         if (VIEWS && lane == 0)
             for (int j = 0; j < A.n_views; ++j) A.view_out[j][out_index] = 2.0f;
         return 2.0f;
     }
-    const float ic = 1.0f / c;
-    float top[MAXV];
+    const double mc = -c64;
+    const int rowb = A.Wp * (int)sizeof(PT);
+    // the top_k smallest view costs, ascending, as bit patterns: costs are
+    // non-negative floats, whose order is that of their bits as unsigned
+    unsigned top[MAXV];
 #pragma unroll
-    for (int i = 0; i < MAXV; ++i) top[i] = 3.0f;
+    for (int i = 0; i < MAXV; ++i) top[i] = 0x40400000u;  // 3.0f
 
     for (int j = 0; j < A.n_views; ++j) {
-        const ViewPoseF &V = A.pose[j];
-        const float t0 = V.t[0] * ic, t1 = V.t[1] * ic, t2 = V.t[2] * ic;
-        const float h00 = fmaf(t0, n0, V.R[0]), h01 = fmaf(t0, n1, V.R[1]), h02 = fmaf(t0, n2, V.R[2]);
-        const float h10 = fmaf(t1, n0, V.R[3]), h11 = fmaf(t1, n1, V.R[4]), h12 = fmaf(t1, n2, V.R[5]);
-        const float h20 = fmaf(t2, n0, V.R[6]), h21 = fmaf(t2, n1, V.R[7]), h22 = fmaf(t2, n2, V.R[8]);
+        const ViewPoseD &V = A.pose[j];
+        const ViewPoseF &Vf = A.posef[j];
+        const __amdgpu_buffer_rsrc_t img = make_rsrc(A.pad[j], A.pad_bytes);
+        // warped centre ray in FP64: M b_p = (-c) R b_p - t (n . b_p), where
+        // M = (-c) R - t n^T is a positive multiple of the plane homography
+        double yc[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double rb = fma(V.R[3 * a], pt.bp64[0], fma(V.R[3 * a + 1], pt.bp64[1], V.R[3 * a + 2] * pt.bp64[2]));
+            yc[a] = fma(mc, rb, -V.t[a] * nbp);
+        }
+        // anchor: the pixel nearest to the warped centre
+        const float lamc = atan2_local((float)yc[0], (float)yc[2]);
+        const float phic = atan2_local((float)-yc[1], __builtin_sqrtf((float)(yc[0] * yc[0] + yc[2] * yc[2])));
+        int U0 = (int)floorf(fmaf(lamc, A.kx, A.cx) + 0.5f);
+        U0 = U0 >= A.W ? U0 - A.W : (U0 < 0 ? U0 + A.W : U0);
+        int V0 = (int)floorf(fmaf(phic, A.ky, A.cy) + 0.5f);
+        V0 = V0 < 0 ? 0 : (V0 > A.H - 1 ? A.H - 1 : V0);
+        const double2 lam0 = A.tab_col64[U0];  // (sin, cos) of the anchor longitude
+        const double2 phi0 = A.tab_row64[V0];  // (sin, cos) of the anchor latitude
+        const int U0p = U0 + (A.W >> 1) + 2;   // anchor in re-laid-out storage
+        const int V0p = V0 + 1;
+        // centre turned about the vertical by -lam0 (FP64). Its longitude is
+        // within half a pixel of lam0, so yr2 > 0 and |yr0| << yr2, and the
+        // horizontal length is yr2 + yr0^2 / (2 yr2) to FP64 precision.
+        const double yr0 = fma(lam0.y, yc[0], -lam0.x * yc[2]);
+        const double yr2 = fma(lam0.x, yc[0], lam0.y * yc[2]);
+        const float y0c = (float)yr0, y2c = (float)yr2;
+        const double hzc = yr2 + (double)(0.5f * y0c * y0c / y2c);
+        // centre: sin and cos of (latitude - phi0), scaled by the ray length
+        const float sdc = (float)fma(-yc[1], phi0.y, -hzc * phi0.x);
+        const float cdc = (float)fma(hzc, phi0.y, -yc[1] * phi0.x);
+        const float hzcf = (float)hzc;
+        const float sp0 = (float)phi0.x, cp0 = (float)phi0.y;
+        const float sl0 = (float)lam0.x, cl0 = (float)lam0.y;
+        // the homography turned by -lam0, in FP32: it only maps the small
+        // offsets of the sample bearings from the centre bearing
+        const float mcf = (float)mc;
+        float h[9];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float m0 = fmaf(mcf, Vf.R[k], -Vf.t[0] * (k == 0 ? n0 : k == 1 ? n1 : n2));
+            const float m1 = fmaf(mcf, Vf.R[3 + k], -Vf.t[1] * (k == 0 ? n0 : k == 1 ? n1 : n2));
+            const float m2 = fmaf(mcf, Vf.R[6 + k], -Vf.t[2] * (k == 0 ? n0 : k == 1 ? n1 : n2));
+            h[k] = fmaf(cl0, m0, -sl0 * m2);
+            h[3 + k] = m1;
+            h[6 + k] = fmaf(sl0, m0, cl0 * m2);
+        }
         float s[SPL];
         float sum = 0.0f;
 #pragma unroll
         for (int i = 0; i < SPL; ++i) {
-            s[i] = 0.0f;
-            if (i < pt.nmine) {
-                const float bx = pt.b[i][0], by = pt.b[i][1], bz = pt.b[i][2];
-                const float y0 = fmaf(h00, bx, fmaf(h01, by, h02 * bz));
-                const float y1 = fmaf(h10, bx, fmaf(h11, by, h12 * bz));
-                const float y2 = fmaf(h20, bx, fmaf(h21, by, h22 * bz));
-                const float lam = atan2f(y0, y2);
-                const float hz = __builtin_sqrtf(fmaf(y0, y0, y2 * y2));
-                const float phi = atan2f(-y1, hz);
-                const float u = fmaf(lam, A.kx, A.cx);
-                const float v = fmaf(phi, A.ky, A.cy);
-                s[i] = bilinear<T>(A.nbr[j], A.W, A.H, u, v);
-                sum += s[i];
-            }
+            const float bx = pt.b[i][0], by = pt.b[i][1], bz = pt.b[i][2];
+            // the turned homography on the offset from the centre bearing
+            const float e0 = fmaf(h[0], bx, fmaf(h[1], by, h[2] * bz));
+            const float e1 = fmaf(h[3], bx, fmaf(h[4], by, h[5] * bz));
+            const float e2 = fmaf(h[6], bx, fmaf(h[7], by, h[8] * bz));
+            const float y0 = y0c + e0, y2 = y2c + e2;
+            const float dl = atan2_local(y0, y2);  // longitude - lam0
+            const float hz = __builtin_sqrtf(fmaf(y0, y0, y2 * y2));
+            // hz - hzc without cancellation
+            const float dhz = fmaf(e0, y0 + y0c, e2 * (y2 + y2c)) * __builtin_amdgcn_rcpf(hz + hzcf);
+            const float sd = fmaf(-dhz, sp0, fmaf(-e1, cp0, sdc));
+            const float cd = fmaf(dhz, cp0, fmaf(-e1, sp0, cdc));
+            const float dp = atan2_local(sd, cd);  // latitude - phi0
+            const float ul = dl * A.kx, vl = dp * A.ky;
+            const float fu = floorf(ul), fv = floorf(vl);
+            const float au = ul - fu, av = vl - fv;
+            // |ul| <= W/2 and the latitude stays within the poles, so these
+            // clamps only guard the storage bounds
+            const int xi = min(max(U0p + (int)fu, 0), A.Wp - 2);
+            const int yi = min(max(V0p + (int)fv, 0), A.H);
+            const int off = (int)(__umul24((unsigned)yi, (unsigned)A.Wp) + (unsigned)xi) * (int)sizeof(PT);
+            const float2 p0 = load_pair<PT>(img, off);
+            const float2 p1 = load_pair<PT>(img, off + rowb);
+            const float top_r = fmaf(au, p0.y - p0.x, p0.x);
+            const float bot_r = fmaf(au, p1.y - p1.x, p1.x);
+            s[i] = fmaf(av, bot_r - top_r, top_r);
+            sum += FULL ? s[i] : s[i] * pt.wt[i];
         }
         sum = quad_sum(sum);
         const float ms = sum * A.inv_P;
         float m2 = 0.0f, cv = 0.0f;
 #pragma unroll
-        for (int i = 0; i < SPL; ++i)
-            if (i < pt.nmine) {
-                const float e = s[i] - ms;
-                m2 = fmaf(e, e, m2);
-                cv = fmaf(pt.rc[i], e, cv);
-            }
+        for (int i = 0; i < SPL; ++i) {
+            const float e = FULL ? s[i] - ms : (s[i] - ms) * pt.wt[i];
+            m2 = fmaf(e, e, m2);
+            cv = fmaf(pt.rc[i], e, cv);
+        }
         m2 = quad_sum(m2);
         cv = quad_sum(cv);
         const float vs = m2 * A.inv_P, cov = cv * A.inv_P;
@@ -289,23 +445,24 @@ __device__ __forceinline__ float evaluate(const SweepArgs &A, const Patch<SPL> &
         if (pt.var_r < A.var_floor || vs < A.var_floor) {
             cj = 2.0f;
         } else {
-            float ncc = cov / sqrtf(pt.var_r * vs);
+            float ncc = cov * __builtin_amdgcn_rsqf(pt.var_r * vs);
             ncc = fminf(fmaxf(ncc, -1.0f), 1.0f);
             cj = 1.0f - ncc;
         }
         if (VIEWS && lane == 0) A.view_out[j][out_index] = cj;
-        // insert into the ascending list of the smallest costs
+        unsigned cb = __float_as_uint(cj);
 #pragma unroll
-        for (int i = 0; i < MAXV; ++i) {
-            const float lo = fminf(top[i], cj), hi = fmaxf(top[i], cj);
-            top[i] = lo;
-            cj = hi;
-        }
+        for (int i = 0; i < MAXV; ++i)
+            if (i < A.top_k) {
+                const unsigned lo = min(top[i], cb), hi = max(top[i], cb);
+                top[i] = lo;
+                cb = hi;
+            }
     }
     float acc = 0.0f;
 #pragma unroll
     for (int i = 0; i < MAXV; ++i)
-        if (i < A.top_k) acc += top[i];
+        if (i < A.top_k) acc += __uint_as_float(top[i]);
     return acc / A.k_float;
 }
 
@@ -335,25 +492,52 @@ __device__ __forceinline__ void tile_pixel(int tid, int &dx, int &dy, int &lane)
 // kernels
 // ---------------------------------------------------------------------------
 
-// Bearing tables in FP64, rounded once.
-__global__ void k_tables(int W, int H, float2 *row, float2 *col)
+// Bearing tables in FP64, also rounded to FP32.
+__global__ void k_tables(int W, int H, float2 *row, float2 *col, double2 *row64, double2 *col64)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const double PI = 3.14159265358979323846;
     if (i < H) {
-        double phi = PI / 2.0 - PI * (i + 0.5) / H;
-        row[i] = make_float2((float)sin(phi), (float)cos(phi));
+        const double phi = PI / 2.0 - PI * (i + 0.5) / H;
+        const double sp = sin(phi), cp = cos(phi);
+        row64[i] = make_double2(sp, cp);
+        row[i] = make_float2((float)sp, (float)cp);
     }
     if (i < W) {
-        double lam = 2.0 * PI * (i + 0.5) / W - PI;
-        col[i] = make_float2((float)sin(lam), (float)cos(lam));
+        const double lam = 2.0 * PI * (i + 0.5) / W - PI;
+        const double sl = sin(lam), cl = cos(lam);
+        col64[i] = make_double2(sl, cl);
+        col[i] = make_float2((float)sl, (float)cl);
     }
 }
 
+// Re-lays out one neighbour image: storage row py holds image row
+// clamp(py - 1, 0, H - 1), storage column px holds image column
+// (px - W/2 - 2) mod W.
+template <int DT>
+__global__ __launch_bounds__(BLOCK) void k_pad(ImgRef src, int W, int H, int Wp,
+                                               typename Storage<DT>::pad_t *dst)
+{
+    using TR = typename Storage<DT>::ref_t;
+    using PT = typename Storage<DT>::pad_t;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)(H + 2) * Wp) return;
+    const int py = (int)(i / Wp), px = (int)(i - (long long)py * Wp);
+    int sx = px - (W >> 1) - 2;
+    sx = sx < 0 ? sx + W : sx;
+    sx = sx >= W ? sx - W : sx;
+    const int sy = py == 0 ? 0 : (py > H ? H - 1 : py - 1);
+    if constexpr (DT == DT_F16)
+        dst[i] = reinterpret_cast<const __half *>(static_cast<const char *>(src.ptr) + (long long)sy * src.pitch)[sx];
+    else
+        dst[i] = (PT)load_px<TR>(src, sx, sy);
+}
+
 // Reference patch mean and variance per valid pixel (two-pass, FP32).
-template <typename T>
+template <int DT>
 __global__ __launch_bounds__(BLOCK) void k_refstats(SweepArgs A)
 {
+    using TR = typename Storage<DT>::ref_t;
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (long long)A.W * A.H) return;
     const int y = (int)(i / A.W), x = (int)(i - (long long)y * A.W);
@@ -364,7 +548,7 @@ __global__ __launch_bounds__(BLOCK) void k_refstats(SweepArgs A)
             int row = q / A.side, col = q - row * A.side;
             int xq = x - A.r + col * A.stride;
             xq = xq < 0 ? xq + A.W : (xq >= A.W ? xq - A.W : xq);
-            sum += load_px<T>(A.ref, xq, y - A.r + row * A.stride);
+            sum += load_px<TR>(A.ref, xq, y - A.r + row * A.stride);
         }
         const float m = sum * A.inv_P;
         float v = 0.0f;
@@ -372,7 +556,7 @@ __global__ __launch_bounds__(BLOCK) void k_refstats(SweepArgs A)
             int row = q / A.side, col = q - row * A.side;
             int xq = x - A.r + col * A.stride;
             xq = xq < 0 ? xq + A.W : (xq >= A.W ? xq - A.W : xq);
-            const float e = load_px<T>(A.ref, xq, y - A.r + row * A.stride) - m;
+            const float e = load_px<TR>(A.ref, xq, y - A.r + row * A.stride) - m;
             v = fmaf(e, e, v);
         }
         out = make_float2(m, v * A.inv_P);
@@ -382,9 +566,11 @@ __global__ __launch_bounds__(BLOCK) void k_refstats(SweepArgs A)
 
 // Random initialisation (Sec. III-B): depth uniform in inverse depth, normal
 // uniform on the sphere turned towards the camera, and its cost.
-template <typename T, int SPL>
+template <int DT, int SPL, bool FULL>
 __global__ __launch_bounds__(BLOCK) void k_init(SweepArgs A)
 {
+    using TR = typename Storage<DT>::ref_t;
+    using PT = typename Storage<DT>::pad_t;
     int tx, ty, dx, dy, lane;
     if (!tile_of_block(A, tx, ty)) return;
     tile_pixel(threadIdx.x, dx, dy, lane);
@@ -399,7 +585,7 @@ __global__ __launch_bounds__(BLOCK) void k_init(SweepArgs A)
         return;
     }
     Patch<SPL> pt;
-    patch_setup<T, SPL>(A, x, y, lane, pt);
+    patch_setup<TR, SPL>(A, x, y, lane, pt);
     float u[4];
     uniforms(A.seed, (unsigned long long)idx, 0ULL, 0ULL, u);
     const float rho = fmaf(u[0], A.inv_dmin - A.inv_dmax, A.inv_dmax);
@@ -419,7 +605,7 @@ __global__ __launch_bounds__(BLOCK) void k_init(SweepArgs A)
         n1 = -pt.bp[1];
         n2 = -pt.bp[2];
     }
-    const float c = evaluate<T, SPL, false>(A, pt, d, n0, n1, n2, lane, 0);
+    const float c = evaluate<PT, SPL, FULL, false>(A, pt, d, n0, n1, n2, lane, 0);
     if (lane == 0) {
         A.state[idx] = make_float4(n0, n1, n2, d);
         A.cost[idx] = c;
@@ -429,9 +615,11 @@ __global__ __launch_bounds__(BLOCK) void k_init(SweepArgs A)
 // One half-sweep (Sec. III-C): propagation from the opposite-colour
 // neighbourhood, then random refinement; strictly cheaper candidates win, the
 // first in table order on ties. Pixels of the other colour are only read.
-template <typename T, int SPL>
+template <int DT, int SPL, bool FULL>
 __global__ __launch_bounds__(BLOCK) void k_halfsweep(SweepArgs A)
 {
+    using TR = typename Storage<DT>::ref_t;
+    using PT = typename Storage<DT>::pad_t;
     int tx, ty, dx, dy, lane;
     if (!tile_of_block(A, tx, ty)) return;
     tile_pixel(threadIdx.x, dx, dy, lane);
@@ -442,7 +630,7 @@ __global__ __launch_bounds__(BLOCK) void k_halfsweep(SweepArgs A)
     const long long idx = (long long)y * A.W + x;
 
     Patch<SPL> pt;
-    patch_setup<T, SPL>(A, x, y, lane, pt);
+    patch_setup<TR, SPL>(A, x, y, lane, pt);
     const float4 cur = A.state[idx];
     float bd = cur.w, bn0 = cur.x, bn1 = cur.y, bn2 = cur.z;
     float bc = A.cost[idx];
@@ -461,7 +649,7 @@ __global__ __launch_bounds__(BLOCK) void k_halfsweep(SweepArgs A)
         if (!(den < 0.0f)) continue;
         const float dd = cq / den;
         if (!(dd >= A.dmin && dd <= A.dmax)) continue;
-        const float c = evaluate<T, SPL, false>(A, pt, dd, sq.x, sq.y, sq.z, lane, 0);
+        const float c = evaluate<PT, SPL, FULL, false>(A, pt, dd, sq.x, sq.y, sq.z, lane, 0);
         if (c < bc) {
             bc = c;
             bd = dd;
@@ -486,7 +674,7 @@ __global__ __launch_bounds__(BLOCK) void k_halfsweep(SweepArgs A)
         m1 /= len;
         m2 /= len;
         if (!(m0 * pt.bp[0] + m1 * pt.bp[1] + m2 * pt.bp[2] < 0.0f)) continue;
-        const float c = evaluate<T, SPL, false>(A, pt, dd, m0, m1, m2, lane, 0);
+        const float c = evaluate<PT, SPL, FULL, false>(A, pt, dd, m0, m1, m2, lane, 0);
         if (c < bc) {
             bc = c;
             bd = dd;
@@ -502,9 +690,11 @@ __global__ __launch_bounds__(BLOCK) void k_halfsweep(SweepArgs A)
 }
 
 // Cost of caller-given hypotheses at every pixel (the matching cost alone).
-template <typename T, int SPL>
+template <int DT, int SPL, bool FULL>
 __global__ __launch_bounds__(BLOCK) void k_eval(SweepArgs A)
 {
+    using TR = typename Storage<DT>::ref_t;
+    using PT = typename Storage<DT>::pad_t;
     int tx, ty, dx, dy, lane;
     if (!tile_of_block(A, tx, ty)) return;
     tile_pixel(threadIdx.x, dx, dy, lane);
@@ -522,12 +712,12 @@ __global__ __launch_bounds__(BLOCK) void k_eval(SweepArgs A)
         return;
     }
     Patch<SPL> pt;
-    patch_setup<T, SPL>(A, x, y, lane, pt);
+    patch_setup<TR, SPL>(A, x, y, lane, pt);
     float c;
     if (A.view_out[0])
-        c = evaluate<T, SPL, true>(A, pt, d, A.in_n0[pin], A.in_n1[pin], A.in_n2[pin], lane, pout);
+        c = evaluate<PT, SPL, FULL, true>(A, pt, d, A.in_n0[pin], A.in_n1[pin], A.in_n2[pin], lane, pout);
     else
-        c = evaluate<T, SPL, false>(A, pt, d, A.in_n0[pin], A.in_n1[pin], A.in_n2[pin], lane, pout);
+        c = evaluate<PT, SPL, FULL, false>(A, pt, d, A.in_n0[pin], A.in_n1[pin], A.in_n2[pin], lane, pout);
     if (lane == 0) A.out_cost[pout] = c;
 }
 
