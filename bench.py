@@ -111,6 +111,9 @@ def main() -> int:
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-budget", type=float, default=12.0,
                     help="wall seconds of oracle work for the CPU baseline (0 = skip)")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="bytes of a plain device-to-device copy run once before the "
+                         "timed region, to calibrate HBM byte counters (0 = none)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the densifier runs one keyframe job per GPU "
@@ -151,6 +154,16 @@ def main() -> int:
 
     def step():
         pms.densify(ref, nbrs, rp, nps, params, maps=maps, map_poses=map_poses, out=out, ctx=ctx)
+
+    if args.copy_probe > 0:
+        n = args.copy_probe // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {n * 4} bytes read and {n * 4} bytes written")
+        del src, dst
 
     log(f"warmup {args.warmup}")
     for _ in range(args.warmup):

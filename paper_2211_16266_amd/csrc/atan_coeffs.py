@@ -1,32 +1,42 @@
 """Derives the atan polynomial used by the kernels' atan2 (pms_kernels.hpp).
 
-atan(t) on [0, 1] is approximated as t + t*s*P(s), s = t^2, with P of
-degree 6 chosen to minimise the maximum RELATIVE error (a linear program on
-4001 points; scipy's HiGHS). The kernels only call it on local angles
-(measured from an anchor pixel), where relative accuracy is what keeps the
-sample coordinates exact to a few 1e-6 px. Run this file to print the
-coefficients (as float32) and the error of the float32 evaluation; the
-kernels hold the printed values.
+atan(t) on [0, tan(pi/8)] is approximated as t + t*s*P(s), s = t^2, with P
+of degree 3 chosen to minimise the maximum RELATIVE error (a linear program
+on 4001 points; scipy's HiGHS). Larger arguments are reduced to this range
+by the kernels (octant symmetry and atan t = pi/4 + atan((t-1)/(t+1))). The
+kernels mostly call it on local angles (measured from an anchor pixel),
+where relative accuracy keeps the sample coordinates exact to a few 1e-6 px.
+Run this file to print the coefficients (as float32) and the error of the
+float32 evaluation; the kernels hold the printed values.
 """
 import numpy as np
 from scipy.optimize import linprog
 
-DEGREE = 6
+DEGREE = 3
+T_MAX = float(np.tan(np.pi / 8))
 
 
 def fit(deg: int = DEGREE, n: int = 4000):
-    t = np.concatenate([np.linspace(1e-4, 1.0, n), [1.0]])
+    t = np.concatenate([np.linspace(1e-5, T_MAX, n), [T_MAX]])
     s = t * t
-    A = np.stack([t * s * s ** k for k in range(deg + 1)], axis=1)
-    f = np.arctan(t) - t
     w = np.arctan(t)
+    # rows divided by atan(t): |A c - f| <= e atan(t) becomes |A' c - f'| <= e
+    A = np.stack([t * s * s ** k for k in range(deg + 1)], axis=1) / w[:, None]
+    f = (np.arctan(t) - t) / w
+    # the errors (~1e-8) sit below the solver's tolerances: scale columns to
+    # unit size and the residuals up
+    cs = np.abs(A).max(axis=0)
+    scale = 1e6
     cobj = np.zeros(deg + 2)
     cobj[-1] = 1.0
-    A_ub = np.vstack([np.hstack([A, -w[:, None]]), np.hstack([-A, -w[:, None]])])
-    b_ub = np.concatenate([f, -f])
+    ones = np.ones((len(t), 1))
+    A_ub = np.vstack([np.hstack([scale * A / cs, -ones]), np.hstack([-scale * A / cs, -ones])])
+    b_ub = np.concatenate([scale * f, -scale * f])
     res = linprog(cobj, A_ub=A_ub, b_ub=b_ub,
                   bounds=[(None, None)] * (deg + 1) + [(0, None)], method="highs")
-    return np.float32(res.x[:-1]), float(res.x[-1])
+    if res.status != 0:
+        raise RuntimeError(res.message)
+    return np.float32(res.x[:-1] / cs), float(res.x[-1]) / scale
 
 
 def eval_f32(c, t):
@@ -40,8 +50,8 @@ def eval_f32(c, t):
 
 if __name__ == "__main__":
     c, e = fit()
-    t = np.linspace(1e-6, 1.0, 2_000_001).astype(np.float32)
+    t = np.linspace(1e-6, T_MAX, 2_000_001).astype(np.float32)
     ref = np.arctan(t.astype(np.float64))
     rel = np.abs(eval_f32(c, t).astype(np.float64) - ref) / ref
-    print("coefficients (c0..c6):", ", ".join(f"{float(x):.9e}f" for x in c))
+    print("coefficients (c0..c3):", ", ".join(f"{float(x):.9e}f" for x in c))
     print(f"exact-arithmetic relative error {e:.3e}, float32 evaluation {rel.max():.3e}")

@@ -371,6 +371,9 @@ void fill_common(pms::SweepArgs &A, const pms_context *ctx, const pms_image *ref
     A.cx = (float)(W / 2.0 - 0.5);
     A.ky = (float)(-H / PI);
     A.cy = (float)(H / 2.0 - 0.5);
+    // chord between bearings r pixels apart in x and y is at most their
+    // angular distance, r (2 pi / W) + r (pi / H) = 2r (2 pi / W)
+    A.patch_chord = (float)(2.0 * A.r * (2.0 * PI / W) * 1.001);
     A.n_offsets = p->n_offsets;
     for (int k = 0; k < p->n_offsets; ++k) {
         A.off_x[k] = p->offsets[k][0];
@@ -402,65 +405,70 @@ void fill_common(pms::SweepArgs &A, const pms_context *ctx, const pms_image *ref
     A.cost = ctx->cost;
 }
 
-// Tiles and grid for a launch over `cols` x `rows` pixels in 8x8 tiles; the
-// grid is padded to a multiple of the 8 XCDs.
+// Lanes per pixel, samples per lane, and whether every lane owns exactly
+// that many samples: a function of the patch size alone, so results never
+// depend on launch shapes.
+struct Variant {
+    int lpp, spl;
+    bool full;
+};
+
+#ifndef PMS_P36_LPP
+#define PMS_P36_LPP 4
+#endif
+
+Variant pick_variant(int P)
+{
+    if (P == 36 && PMS_P36_LPP == 2) return {2, 18, true};
+    if (P % 4 == 0 && (P / 4 == 9 || P / 4 == 16)) return {4, P / 4, true};
+    const int need = (P + 3) / 4;
+    return {4, need <= 4 ? 4 : need <= 9 ? 9 : need <= 13 ? 13 : 16, false};
+}
+
+// Tiles and grid for a launch over `cols` x `rows` pixels in (32/LPP) x 8
+// tiles; the grid is padded to a multiple of the 8 XCDs.
 dim3 tile_grid(pms::SweepArgs &A, int cols, int rows)
 {
-    A.tiles_x = (cols + pms::TILE - 1) / pms::TILE;
-    A.tiles_y = (rows + pms::TILE - 1) / pms::TILE;
+    const int tx = 32 / pick_variant(A.P).lpp;
+    A.tiles_x = (cols + tx - 1) / tx;
+    A.tiles_y = (rows + pms::TILE_Y - 1) / pms::TILE_Y;
     const int tiles = A.tiles_x * A.tiles_y;
     A.tiles_per_xcd = (tiles + 7) / 8;
     return dim3(8 * A.tiles_per_xcd);
 }
 
-// Samples per lane and whether every lane owns exactly that many: the
-// smallest compiled variant for P samples over 4 lanes.
-void pick_variant(int P, int *spl, bool *full)
-{
-    const int need = (P + pms::LPP - 1) / pms::LPP;
-    const bool even = P % pms::LPP == 0;
-    if (even && (need == 9 || need == 16)) {
-        *spl = need;
-        *full = true;
-        return;
-    }
-    *full = false;
-    *spl = need <= 4 ? 4 : need <= 9 ? 9 : need <= 13 ? 13 : 16;
-}
-
-template <int DT, int SPL, bool FULL>
+template <int DT, int LPP, int SPL, bool FULL>
 void launch_kernel(int kind, const pms::SweepArgs &A, dim3 grid, hipStream_t s)
 {
     switch (kind) {
-    case KK_INIT: hipLaunchKernelGGL((pms::k_init<DT, SPL, FULL>), grid, dim3(pms::BLOCK), 0, s, A); break;
-    case KK_HALFSWEEP: hipLaunchKernelGGL((pms::k_halfsweep<DT, SPL, FULL>), grid, dim3(pms::BLOCK), 0, s, A); break;
-    case KK_EVAL: hipLaunchKernelGGL((pms::k_eval<DT, SPL, FULL>), grid, dim3(pms::BLOCK), 0, s, A); break;
+    case KK_INIT: hipLaunchKernelGGL((pms::k_init<DT, LPP, SPL, FULL>), grid, dim3(pms::BLOCK), 0, s, A); break;
+    case KK_HALFSWEEP: hipLaunchKernelGGL((pms::k_halfsweep<DT, LPP, SPL, FULL>), grid, dim3(pms::BLOCK), 0, s, A); break;
+    case KK_EVAL: hipLaunchKernelGGL((pms::k_eval<DT, LPP, SPL, FULL>), grid, dim3(pms::BLOCK), 0, s, A); break;
     default: break;
     }
 }
 
 template <int DT>
-void launch_variant(int kind, int spl, bool full, const pms::SweepArgs &A, dim3 grid, hipStream_t s)
+void launch_variant(int kind, const Variant &v, const pms::SweepArgs &A, dim3 grid, hipStream_t s)
 {
-    if (full && spl == 9) launch_kernel<DT, 9, true>(kind, A, grid, s);
-    else if (full && spl == 16) launch_kernel<DT, 16, true>(kind, A, grid, s);
-    else if (spl == 4) launch_kernel<DT, 4, false>(kind, A, grid, s);
-    else if (spl == 9) launch_kernel<DT, 9, false>(kind, A, grid, s);
-    else if (spl == 13) launch_kernel<DT, 13, false>(kind, A, grid, s);
-    else launch_kernel<DT, 16, false>(kind, A, grid, s);
+    if (v.lpp == 2) launch_kernel<DT, 2, 18, true>(kind, A, grid, s);
+    else if (v.full && v.spl == 9) launch_kernel<DT, 4, 9, true>(kind, A, grid, s);
+    else if (v.full && v.spl == 16) launch_kernel<DT, 4, 16, true>(kind, A, grid, s);
+    else if (v.spl == 4) launch_kernel<DT, 4, 4, false>(kind, A, grid, s);
+    else if (v.spl == 9) launch_kernel<DT, 4, 9, false>(kind, A, grid, s);
+    else if (v.spl == 13) launch_kernel<DT, 4, 13, false>(kind, A, grid, s);
+    else launch_kernel<DT, 4, 16, false>(kind, A, grid, s);
 }
 
 pms_status launch(pms_context *ctx, int kind, int dtype, const pms::SweepArgs &A, dim3 grid,
                   hipStream_t s)
 {
     LaunchTimer timer(ctx, kind, s);
-    int spl;
-    bool full;
-    pick_variant(A.P, &spl, &full);
+    const Variant v = pick_variant(A.P);
     switch (dtype) {
-    case PMS_F32: launch_variant<pms::DT_F32>(kind, spl, full, A, grid, s); break;
-    case PMS_F16: launch_variant<pms::DT_F16>(kind, spl, full, A, grid, s); break;
-    default: launch_variant<pms::DT_U8>(kind, spl, full, A, grid, s); break;
+    case PMS_F32: launch_variant<pms::DT_F32>(kind, v, A, grid, s); break;
+    case PMS_F16: launch_variant<pms::DT_F16>(kind, v, A, grid, s); break;
+    default: launch_variant<pms::DT_U8>(kind, v, A, grid, s); break;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(ctx, e, kKernelNames[kind]);

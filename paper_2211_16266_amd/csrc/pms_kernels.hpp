@@ -2,13 +2,14 @@
 // densification (Surmann et al., Sec. III-B/C). Included once, by pms.hip.
 //
 // Work decomposition
-//   * One reference pixel is served by LPP = 4 adjacent lanes of a wave64
-//     (one DPP quad). Each lane owns every 4th patch sample: its bearing,
-//     its centred reference value and, per view, its warped neighbour value
-//     stay in VGPRs; patch sums are reduced inside the quad with two DPP
-//     quad_perm adds, so the reduction order depends on the patch only.
-//   * A workgroup of 256 threads covers an 8x8 tile of pixels of one colour
-//     (red-black sweep) or of all pixels (init / cost evaluation); tiles are
+//   * One reference pixel is served by LPP (2 or 4) adjacent lanes of a
+//     wave64 inside one DPP quad. Each lane owns every LPP-th patch sample:
+//     its bearing, its centred reference value and, per view, its warped
+//     neighbour value stay in VGPRs; patch sums are reduced inside the group
+//     with quad_perm DPP adds, so the reduction order depends on the patch
+//     only. LPP is chosen from the patch size alone.
+//   * A workgroup of 256 threads covers a (32/LPP) x 8 tile of pixels of one
+//     colour (red-black sweep) or of all pixels (init / cost evaluation); tiles are
 //     handed out so that each XCD walks a contiguous band of rows and keeps
 //     the matching part of the neighbour images in its own L2.
 //   * Neighbour images are re-laid out once per call: every row is repeated
@@ -48,14 +49,23 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace pms {
 
-constexpr int LPP = 4;        // lanes per pixel (one DPP quad)
 constexpr int MAXV = 8;       // neighbour views per launch
 constexpr int MAXOFF = 16;    // propagation offsets
 constexpr int MAXTRIAL = 16;  // refinement trials
-constexpr int TILE = 8;       // 8x8 pixel tile per 256-thread workgroup
+constexpr int TILE_Y = 8;     // tile rows per 256-thread workgroup
+template <int LPP>
+constexpr int tile_x() { return 32 / LPP; }  // tile columns
 constexpr int BLOCK = 256;
+
+// Occupancy target of the PatchMatch kernels (waves per SIMD): 4 for up to
+// 9 samples per lane, where the compiler would otherwise settle for 3 waves
+// to avoid a couple of spill slots outside the sample loop; the larger
+// variants keep the compiler's choice.
+#define PMS_OCCUPANCY(SPL) __attribute__((amdgpu_waves_per_eu((SPL) <= 9 ? 4 : 1, 8)))
 // Re-laid-out neighbour image: H + 2 rows of 2W + 4 values;
 // logical column x is stored at x + W/2 + 2, logical row y at y + 1.
 
@@ -86,6 +96,7 @@ struct SweepArgs {
     float var_floor;
     float dmin, dmax, inv_dmin, inv_dmax;
     float kx, cx, ky, cy;  // u = lam * kx + cx, v = phi * ky + cy
+    float patch_chord;     // bound on |b_q - b_p| over the patch
     int n_offsets;
     int off_x[MAXOFF], off_y[MAXOFF];
     int refine_trials;
@@ -137,19 +148,22 @@ struct Storage<DT_U8> {
 // small helpers
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ float quad_sum(float v)
+// Sum over the LPP lanes of a pixel: quad_perm [1,0,3,2], then (LPP = 4)
+// [2,3,0,1]. Every lane of the group ends with the same bits
+// ((a+b)+(c+d) == (b+a)+(d+c) exactly).
+template <int LPP>
+__device__ __forceinline__ float group_sum(float v)
 {
-    // quad_perm [1,0,3,2] then [2,3,0,1]: every lane of the quad ends with the
-    // same bits ((a+b)+(c+d) == (b+a)+(d+c) exactly)
     v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, true));
-    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, true));
+    if (LPP == 4) v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, true));
     return v;
 }
 
-__device__ __forceinline__ int quad_and(int v)
+template <int LPP>
+__device__ __forceinline__ int group_and(int v)
 {
     v &= __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true);
-    v &= __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true);
+    if (LPP == 4) v &= __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true);
     return v;
 }
 
@@ -206,28 +220,44 @@ __device__ __forceinline__ void bearing(const SweepArgs &A, int x, int y, float 
     b[2] = rw.y * cl.y;
 }
 
-// atan2 for the sample coordinates: octant reduction to t in [0, 1] and
-// atan(t) = t + t s P(s), s = t^2, with a degree-6 P fitted for minimum
-// relative error (3.5e-7 when evaluated in FP32; fitted by atan_coeffs.py).
-// Both arguments zero give 0.
-__device__ __forceinline__ float atan2_local(float y, float x)
+// atan(t) for |t| <= tan(pi/8): t + t s P(s), s = t^2, with a degree-3 P
+// fitted for minimum relative error (8e-8 in FP32; atan_coeffs.py). Odd in
+// t bit for bit: round-to-nearest is symmetric.
+constexpr float TAN_PI_8 = 0.41421356f;
+// tan(pi/8) less a margin for the rounding of the range test itself
+constexpr float SHORT_RANGE = 0.4141f;
+
+__device__ __forceinline__ float atan_core(float t)
+{
+    const float s = t * t;
+    float p = fmaf(s, 8.053722978e-02f, -1.387767941e-01f);
+    p = fmaf(p, s, 1.997770965e-01f);
+    p = fmaf(p, s, -3.333294988e-01f);
+    return fmaf(t * s, p, t);
+}
+
+// atan2 for any arguments (both zero give 0): octant reduction to t in
+// [0, 1], then t > tan(pi/8) is mapped to (t - 1) / (t + 1) in (-tan(pi/8), 0]
+// with atan t = pi/4 + atan((t - 1) / (t + 1)).
+__device__ __forceinline__ float atan2_full(float y, float x)
 {
     const float ax = fabsf(x), ay = fabsf(y);
     const float mx = fmaxf(fmaxf(ax, ay), 1e-30f);
     const float mn = fminf(ax, ay);
     const float t = mn * __builtin_amdgcn_rcpf(mx);
-    const float s = t * t;
-    float p = fmaf(s, -4.582961090e-03f, 2.390408702e-02f);
-    p = fmaf(p, s, -5.909144133e-02f);
-    p = fmaf(p, s, 9.897302091e-02f);
-    p = fmaf(p, s, -1.402012706e-01f);
-    p = fmaf(p, s, 1.997216046e-01f);
-    p = fmaf(p, s, -3.333249390e-01f);
-    float r = fmaf(t * s, p, t);
+    const bool big = t > TAN_PI_8;
+    const float u = big ? (t - 1.0f) * __builtin_amdgcn_rcpf(t + 1.0f) : t;
+    float r = atan_core(u) + (big ? 0.78539816339744831f : 0.0f);
     r = ay > ax ? 1.57079632679489662f - r : r;
     r = x < 0.0f ? 3.14159265358979324f - r : r;
     return copysignf(r, y);
 }
+
+// For x > 1e-30 and |y| rcp(x) <= tan(pi/8), atan2_full(y, x) computes
+// exactly copysign(atan_core(|y| rcp(x)), y) = atan_core(y rcp(x)). Sample
+// angles measured from the anchor take this short form when a bound shows
+// that all of them qualify; the forms agree bit for bit where both apply,
+// so no result depends on which path a wave takes.
 
 // Philox4x64-10 (Salmon et al., SC'11), counter (c0, c1, c2, c3), key (k0, k1).
 __device__ __forceinline__ void philox4x64_10(unsigned long long k0, unsigned long long k1,
@@ -273,7 +303,7 @@ struct Patch {
     float var_r;      // reference patch variance
 };
 
-template <typename TR, int SPL>
+template <typename TR, int LPP, int SPL>
 __device__ __forceinline__ void patch_setup(const SweepArgs &A, int x, int y, int lane,
                                             Patch<SPL> &pt)
 {
@@ -314,14 +344,21 @@ __device__ __forceinline__ void patch_setup(const SweepArgs &A, int x, int y, in
 
 // Aggregated cost of plane (d, n) at the pixel of `pt`: per view, warp every
 // sample, bilinear-sample the neighbour, two-pass NCC, cost = 1 - NCC or 2
-// when invalid; then the mean of the top_k smallest view costs. All 4 lanes
-// of the quad return the same value. FULL: every lane owns SPL samples (P is
-// a multiple of 4), so no slot is masked. When VIEWS is set, lane 0 of the
-// quad writes each view's cost to A.view_out[j][out_index].
-template <typename PT, int SPL, bool FULL, bool VIEWS>
+// when invalid; then the mean of the top_k smallest view costs. All lanes of
+// the pixel return the same value. FULL: every lane owns SPL samples (P is
+// a multiple of LPP), so no slot is masked. When VIEWS is set, the pixel's
+// first lane writes each view's cost to A.view_out[j][out_index].
+//
+// `bound`: the caller only uses the result if it is below `bound`. Once the
+// views still to come are fewer than top_k, the aggregate is at least the
+// same ascending sum with those views at cost 0; when that is already
+// >= bound the remaining views are skipped and a value >= bound returned.
+// Float addition and division round monotonically, so every decision the
+// caller takes is the one the full evaluation gives.
+template <typename PT, int LPP, int SPL, bool FULL, bool VIEWS>
 __device__ __forceinline__ float evaluate(const SweepArgs &A, const Patch<SPL> &pt, float d,
                                           float n0, float n1, float n2, int lane,
-                                          long long out_index)
+                                          long long out_index, float bound = 3.0f)
 {
     const double n64[3] = {(double)n0, (double)n1, (double)n2};
     const double nbp = n64[0] * pt.bp64[0] + n64[1] * pt.bp64[1] + n64[2] * pt.bp64[2];
@@ -334,7 +371,7 @@ __device__ __forceinline__ float evaluate(const SweepArgs &A, const Patch<SPL> &
         const float den = fmaf(n0, pt.b[i][0], fmaf(n1, pt.b[i][1], fmaf(n2, pt.b[i][2], nbpf)));
         ok &= FULL ? (den < 0.0f) : (den < 0.0f || pt.wt[i] == 0.0f);
     }
-    ok = quad_and(ok);
+    ok = group_and<LPP>(ok);
     if (!ok) {
         if (VIEWS && lane == 0)
             for (int j = 0; j < A.n_views; ++j) A.view_out[j][out_index] = 2.0f;
@@ -361,8 +398,8 @@ __device__ __forceinline__ float evaluate(const SweepArgs &A, const Patch<SPL> &
             yc[a] = fma(mc, rb, -V.t[a] * nbp);
         }
         // anchor: the pixel nearest to the warped centre
-        const float lamc = atan2_local((float)yc[0], (float)yc[2]);
-        const float phic = atan2_local((float)-yc[1], __builtin_sqrtf((float)(yc[0] * yc[0] + yc[2] * yc[2])));
+        const float lamc = atan2_full((float)yc[0], (float)yc[2]);
+        const float phic = atan2_full((float)-yc[1], __builtin_amdgcn_sqrtf((float)(yc[0] * yc[0] + yc[2] * yc[2])));
         int U0 = (int)floorf(fmaf(lamc, A.kx, A.cx) + 0.5f);
         U0 = U0 >= A.W ? U0 - A.W : (U0 < 0 ? U0 + A.W : U0);
         int V0 = (int)floorf(fmaf(phic, A.ky, A.cy) + 0.5f);
@@ -388,6 +425,7 @@ __device__ __forceinline__ float evaluate(const SweepArgs &A, const Patch<SPL> &
         // offsets of the sample bearings from the centre bearing
         const float mcf = (float)mc;
         float h[9];
+        float mf2 = 0.0f;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const float m0 = fmaf(mcf, Vf.R[k], -Vf.t[0] * (k == 0 ? n0 : k == 1 ? n1 : n2));
@@ -396,40 +434,88 @@ __device__ __forceinline__ float evaluate(const SweepArgs &A, const Patch<SPL> &
             h[k] = fmaf(cl0, m0, -sl0 * m2);
             h[3 + k] = m1;
             h[6 + k] = fmaf(sl0, m0, cl0 * m2);
+            mf2 = fmaf(m0, m0, fmaf(m1, m1, fmaf(m2, m2, mf2)));
         }
         float s[SPL];
         float sum = 0.0f;
-#pragma unroll
-        for (int i = 0; i < SPL; ++i) {
-            const float bx = pt.b[i][0], by = pt.b[i][1], bz = pt.b[i][2];
-            // the turned homography on the offset from the centre bearing
-            const float e0 = fmaf(h[0], bx, fmaf(h[1], by, h[2] * bz));
-            const float e1 = fmaf(h[3], bx, fmaf(h[4], by, h[5] * bz));
-            const float e2 = fmaf(h[6], bx, fmaf(h[7], by, h[8] * bz));
-            const float y0 = y0c + e0, y2 = y2c + e2;
-            const float dl = atan2_local(y0, y2);  // longitude - lam0
-            const float hz = __builtin_sqrtf(fmaf(y0, y0, y2 * y2));
-            // hz - hzc without cancellation
-            const float dhz = fmaf(e0, y0 + y0c, e2 * (y2 + y2c)) * __builtin_amdgcn_rcpf(hz + hzcf);
-            const float sd = fmaf(-dhz, sp0, fmaf(-e1, cp0, sdc));
-            const float cd = fmaf(dhz, cp0, fmaf(-e1, sp0, cdc));
-            const float dp = atan2_local(sd, cd);  // latitude - phi0
-            const float ul = dl * A.kx, vl = dp * A.ky;
-            const float fu = floorf(ul), fv = floorf(vl);
-            const float au = ul - fu, av = vl - fv;
-            // |ul| <= W/2 and the latitude stays within the poles, so these
-            // clamps only guard the storage bounds
-            const int xi = min(max(U0p + (int)fu, 0), A.Wp - 2);
-            const int yi = min(max(V0p + (int)fv, 0), A.H);
-            const int off = (int)(__umul24((unsigned)yi, (unsigned)A.Wp) + (unsigned)xi) * (int)sizeof(PT);
-            const float2 p0 = load_pair<PT>(img, off);
-            const float2 p1 = load_pair<PT>(img, off + rowb);
-            const float top_r = fmaf(au, p0.y - p0.x, p0.x);
-            const float bot_r = fmaf(au, p1.y - p1.x, p1.x);
-            s[i] = fmaf(av, bot_r - top_r, top_r);
-            sum += FULL ? s[i] : s[i] * pt.wt[i];
+        // Every sample offset e = h (b_q - b_p) satisfies |e| <= |M|_F dmax
+        // (turning keeps the norm). If the centre and that bound keep both
+        // angles of every sample in the short form's range, the wave takes
+        // the short form, which then equals the general one bit for bit.
+        const float E = __builtin_amdgcn_sqrtf(mf2) * A.patch_chord;
+        const float lon_den = y2c - E, lat_den = cdc - E;
+        const bool short_ok = lon_den > 1e-30f && fabsf(y0c) + E <= SHORT_RANGE * lon_den &&
+                              lat_den > 1e-30f && fabsf(sdc) + E <= SHORT_RANGE * lat_den;
+        // (compiled in for up to 9 samples per lane only: the larger variants
+        // cannot hold both copies at their occupancy)
+        if (SPL <= 9 && __all(short_ok)) {
+    #pragma unroll
+            for (int i = 0; i < SPL; ++i) {
+                const float bx = pt.b[i][0], by = pt.b[i][1], bz = pt.b[i][2];
+                // the turned homography on the offset from the centre bearing
+                const float e0 = fmaf(h[0], bx, fmaf(h[1], by, h[2] * bz));
+                const float e1 = fmaf(h[3], bx, fmaf(h[4], by, h[5] * bz));
+                const float e2 = fmaf(h[6], bx, fmaf(h[7], by, h[8] * bz));
+                const float y0 = y0c + e0, y2 = y2c + e2;
+                const float hz = __builtin_amdgcn_sqrtf(fmaf(y0, y0, y2 * y2));
+                // hz - hzc without cancellation
+                const float dhz = fmaf(e0, y0 + y0c, e2 * (y2 + y2c)) * __builtin_amdgcn_rcpf(hz + hzcf);
+                const float sd = fmaf(-dhz, sp0, fmaf(-e1, cp0, sdc));
+                const float cd = fmaf(dhz, cp0, fmaf(-e1, sp0, cdc));
+                // longitude - lam0 and latitude - phi0
+                const float dl = atan_core(y0 * __builtin_amdgcn_rcpf(y2));
+                const float dp = atan_core(sd * __builtin_amdgcn_rcpf(cd));
+                const float ul = dl * A.kx, vl = dp * A.ky;
+                const float fu = floorf(ul), fv = floorf(vl);
+                const float au = ul - fu, av = vl - fv;
+                // |ul| <= W/2 keeps the column inside the repeated storage; the
+                // latitude stays within the poles, so this clamp only guards
+                // against rounding
+                const int xi = U0p + (int)fu;
+                const int yi = min(max(V0p + (int)fv, 0), A.H);
+                const int off = (int)(__umul24((unsigned)yi, (unsigned)A.Wp) + (unsigned)xi) * (int)sizeof(PT);
+                const float2 p0 = load_pair<PT>(img, off);
+                const float2 p1 = load_pair<PT>(img, off + rowb);
+                const float top_r = fmaf(au, p0.y - p0.x, p0.x);
+                const float bot_r = fmaf(au, p1.y - p1.x, p1.x);
+                s[i] = fmaf(av, bot_r - top_r, top_r);
+                sum += FULL ? s[i] : s[i] * pt.wt[i];
+            }
+        } else {
+    #pragma unroll
+            for (int i = 0; i < SPL; ++i) {
+                const float bx = pt.b[i][0], by = pt.b[i][1], bz = pt.b[i][2];
+                // the turned homography on the offset from the centre bearing
+                const float e0 = fmaf(h[0], bx, fmaf(h[1], by, h[2] * bz));
+                const float e1 = fmaf(h[3], bx, fmaf(h[4], by, h[5] * bz));
+                const float e2 = fmaf(h[6], bx, fmaf(h[7], by, h[8] * bz));
+                const float y0 = y0c + e0, y2 = y2c + e2;
+                const float hz = __builtin_amdgcn_sqrtf(fmaf(y0, y0, y2 * y2));
+                // hz - hzc without cancellation
+                const float dhz = fmaf(e0, y0 + y0c, e2 * (y2 + y2c)) * __builtin_amdgcn_rcpf(hz + hzcf);
+                const float sd = fmaf(-dhz, sp0, fmaf(-e1, cp0, sdc));
+                const float cd = fmaf(dhz, cp0, fmaf(-e1, sp0, cdc));
+                // longitude - lam0 and latitude - phi0
+                const float dl = atan2_full(y0, y2);
+                const float dp = atan2_full(sd, cd);
+                const float ul = dl * A.kx, vl = dp * A.ky;
+                const float fu = floorf(ul), fv = floorf(vl);
+                const float au = ul - fu, av = vl - fv;
+                // |ul| <= W/2 keeps the column inside the repeated storage; the
+                // latitude stays within the poles, so this clamp only guards
+                // against rounding
+                const int xi = U0p + (int)fu;
+                const int yi = min(max(V0p + (int)fv, 0), A.H);
+                const int off = (int)(__umul24((unsigned)yi, (unsigned)A.Wp) + (unsigned)xi) * (int)sizeof(PT);
+                const float2 p0 = load_pair<PT>(img, off);
+                const float2 p1 = load_pair<PT>(img, off + rowb);
+                const float top_r = fmaf(au, p0.y - p0.x, p0.x);
+                const float bot_r = fmaf(au, p1.y - p1.x, p1.x);
+                s[i] = fmaf(av, bot_r - top_r, top_r);
+                sum += FULL ? s[i] : s[i] * pt.wt[i];
+            }
         }
-        sum = quad_sum(sum);
+        sum = group_sum<LPP>(sum);
         const float ms = sum * A.inv_P;
         float m2 = 0.0f, cv = 0.0f;
 #pragma unroll
@@ -438,8 +524,8 @@ __device__ __forceinline__ float evaluate(const SweepArgs &A, const Patch<SPL> &
             m2 = fmaf(e, e, m2);
             cv = fmaf(pt.rc[i], e, cv);
         }
-        m2 = quad_sum(m2);
-        cv = quad_sum(cv);
+        m2 = group_sum<LPP>(m2);
+        cv = group_sum<LPP>(cv);
         const float vs = m2 * A.inv_P, cov = cv * A.inv_P;
         float cj;
         if (pt.var_r < A.var_floor || vs < A.var_floor) {
@@ -458,6 +544,16 @@ __device__ __forceinline__ float evaluate(const SweepArgs &A, const Patch<SPL> &
                 top[i] = lo;
                 cb = hi;
             }
+        if (!VIEWS) {
+            const int have = A.top_k - (A.n_views - 1 - j);  // evaluated costs in the bound
+            if (have > 0) {
+                float lb = 0.0f;
+#pragma unroll
+                for (int i = 0; i < MAXV; ++i)
+                    if (i < have) lb += __uint_as_float(top[i]);
+                if (lb / A.k_float >= bound) return lb / A.k_float;
+            }
+        }
     }
     float acc = 0.0f;
 #pragma unroll
@@ -478,14 +574,17 @@ __device__ __forceinline__ bool tile_of_block(const SweepArgs &A, int &tx, int &
     return true;
 }
 
-// Position of this thread's pixel inside an 8x8 tile: 4 waves of 4x4 pixels.
+// Position of this thread's pixel inside a (32/LPP) x 8 tile: 4 waves of
+// (16/LPP) x 4 pixels.
+template <int LPP>
 __device__ __forceinline__ void tile_pixel(int tid, int &dx, int &dy, int &lane)
 {
+    constexpr int WX = 16 / LPP;
     lane = tid & (LPP - 1);
-    const int pix = tid >> 2;
-    const int wave = pix >> 4;
-    dx = ((wave & 1) << 2) + (pix & 3);
-    dy = ((wave >> 1) << 2) + ((pix >> 2) & 3);
+    const int wave = tid >> 6;
+    const int piw = (tid & 63) / LPP;
+    dx = (wave & 1) * WX + piw % WX;
+    dy = ((wave >> 1) << 2) + piw / WX;
 }
 
 // ---------------------------------------------------------------------------
@@ -566,15 +665,15 @@ __global__ __launch_bounds__(BLOCK) void k_refstats(SweepArgs A)
 
 // Random initialisation (Sec. III-B): depth uniform in inverse depth, normal
 // uniform on the sphere turned towards the camera, and its cost.
-template <int DT, int SPL, bool FULL>
-__global__ __launch_bounds__(BLOCK) void k_init(SweepArgs A)
+template <int DT, int LPP, int SPL, bool FULL>
+__global__ __launch_bounds__(BLOCK) PMS_OCCUPANCY(SPL) void k_init(SweepArgs A)
 {
     using TR = typename Storage<DT>::ref_t;
     using PT = typename Storage<DT>::pad_t;
     int tx, ty, dx, dy, lane;
     if (!tile_of_block(A, tx, ty)) return;
-    tile_pixel(threadIdx.x, dx, dy, lane);
-    const int x = tx * TILE + dx, y = ty * TILE + dy;
+    tile_pixel<LPP>(threadIdx.x, dx, dy, lane);
+    const int x = tx * tile_x<LPP>() + dx, y = ty * TILE_Y + dy;
     if (x >= A.W || y >= A.H) return;
     const long long idx = (long long)y * A.W + x;
     if (y < A.r || y > A.H - 1 - A.r) {
@@ -585,7 +684,7 @@ __global__ __launch_bounds__(BLOCK) void k_init(SweepArgs A)
         return;
     }
     Patch<SPL> pt;
-    patch_setup<TR, SPL>(A, x, y, lane, pt);
+    patch_setup<TR, LPP, SPL>(A, x, y, lane, pt);
     float u[4];
     uniforms(A.seed, (unsigned long long)idx, 0ULL, 0ULL, u);
     const float rho = fmaf(u[0], A.inv_dmin - A.inv_dmax, A.inv_dmax);
@@ -605,7 +704,7 @@ __global__ __launch_bounds__(BLOCK) void k_init(SweepArgs A)
         n1 = -pt.bp[1];
         n2 = -pt.bp[2];
     }
-    const float c = evaluate<PT, SPL, FULL, false>(A, pt, d, n0, n1, n2, lane, 0);
+    const float c = evaluate<PT, LPP, SPL, FULL, false>(A, pt, d, n0, n1, n2, lane, 0);
     if (lane == 0) {
         A.state[idx] = make_float4(n0, n1, n2, d);
         A.cost[idx] = c;
@@ -615,22 +714,22 @@ __global__ __launch_bounds__(BLOCK) void k_init(SweepArgs A)
 // One half-sweep (Sec. III-C): propagation from the opposite-colour
 // neighbourhood, then random refinement; strictly cheaper candidates win, the
 // first in table order on ties. Pixels of the other colour are only read.
-template <int DT, int SPL, bool FULL>
-__global__ __launch_bounds__(BLOCK) void k_halfsweep(SweepArgs A)
+template <int DT, int LPP, int SPL, bool FULL>
+__global__ __launch_bounds__(BLOCK) PMS_OCCUPANCY(SPL) void k_halfsweep(SweepArgs A)
 {
     using TR = typename Storage<DT>::ref_t;
     using PT = typename Storage<DT>::pad_t;
     int tx, ty, dx, dy, lane;
     if (!tile_of_block(A, tx, ty)) return;
-    tile_pixel(threadIdx.x, dx, dy, lane);
-    const int k = tx * TILE + dx;
-    const int y = A.r + ty * TILE + dy;
+    tile_pixel<LPP>(threadIdx.x, dx, dy, lane);
+    const int k = tx * tile_x<LPP>() + dx;
+    const int y = A.r + ty * TILE_Y + dy;
     if (k >= (A.W >> 1) || y > A.H - 1 - A.r) return;
     const int x = 2 * k + ((y + A.colour) & 1);
     const long long idx = (long long)y * A.W + x;
 
     Patch<SPL> pt;
-    patch_setup<TR, SPL>(A, x, y, lane, pt);
+    patch_setup<TR, LPP, SPL>(A, x, y, lane, pt);
     const float4 cur = A.state[idx];
     float bd = cur.w, bn0 = cur.x, bn1 = cur.y, bn2 = cur.z;
     float bc = A.cost[idx];
@@ -649,7 +748,7 @@ __global__ __launch_bounds__(BLOCK) void k_halfsweep(SweepArgs A)
         if (!(den < 0.0f)) continue;
         const float dd = cq / den;
         if (!(dd >= A.dmin && dd <= A.dmax)) continue;
-        const float c = evaluate<PT, SPL, FULL, false>(A, pt, dd, sq.x, sq.y, sq.z, lane, 0);
+        const float c = evaluate<PT, LPP, SPL, FULL, false>(A, pt, dd, sq.x, sq.y, sq.z, lane, 0, bc);
         if (c < bc) {
             bc = c;
             bd = dd;
@@ -674,7 +773,7 @@ __global__ __launch_bounds__(BLOCK) void k_halfsweep(SweepArgs A)
         m1 /= len;
         m2 /= len;
         if (!(m0 * pt.bp[0] + m1 * pt.bp[1] + m2 * pt.bp[2] < 0.0f)) continue;
-        const float c = evaluate<PT, SPL, FULL, false>(A, pt, dd, m0, m1, m2, lane, 0);
+        const float c = evaluate<PT, LPP, SPL, FULL, false>(A, pt, dd, m0, m1, m2, lane, 0, bc);
         if (c < bc) {
             bc = c;
             bd = dd;
@@ -690,15 +789,15 @@ __global__ __launch_bounds__(BLOCK) void k_halfsweep(SweepArgs A)
 }
 
 // Cost of caller-given hypotheses at every pixel (the matching cost alone).
-template <int DT, int SPL, bool FULL>
-__global__ __launch_bounds__(BLOCK) void k_eval(SweepArgs A)
+template <int DT, int LPP, int SPL, bool FULL>
+__global__ __launch_bounds__(BLOCK) PMS_OCCUPANCY(SPL) void k_eval(SweepArgs A)
 {
     using TR = typename Storage<DT>::ref_t;
     using PT = typename Storage<DT>::pad_t;
     int tx, ty, dx, dy, lane;
     if (!tile_of_block(A, tx, ty)) return;
-    tile_pixel(threadIdx.x, dx, dy, lane);
-    const int x = tx * TILE + dx, y = ty * TILE + dy;
+    tile_pixel<LPP>(threadIdx.x, dx, dy, lane);
+    const int x = tx * tile_x<LPP>() + dx, y = ty * TILE_Y + dy;
     if (x >= A.W || y >= A.H) return;
     const long long pin = (long long)y * A.in_pitch + x;
     const long long pout = (long long)y * A.out_pitch + x;
@@ -712,12 +811,12 @@ __global__ __launch_bounds__(BLOCK) void k_eval(SweepArgs A)
         return;
     }
     Patch<SPL> pt;
-    patch_setup<TR, SPL>(A, x, y, lane, pt);
+    patch_setup<TR, LPP, SPL>(A, x, y, lane, pt);
     float c;
     if (A.view_out[0])
-        c = evaluate<PT, SPL, FULL, true>(A, pt, d, A.in_n0[pin], A.in_n1[pin], A.in_n2[pin], lane, pout);
+        c = evaluate<PT, LPP, SPL, FULL, true>(A, pt, d, A.in_n0[pin], A.in_n1[pin], A.in_n2[pin], lane, pout);
     else
-        c = evaluate<PT, SPL, FULL, false>(A, pt, d, A.in_n0[pin], A.in_n1[pin], A.in_n2[pin], lane, pout);
+        c = evaluate<PT, LPP, SPL, FULL, false>(A, pt, d, A.in_n0[pin], A.in_n1[pin], A.in_n2[pin], lane, pout);
     if (lane == 0) A.out_cost[pout] = c;
 }
 

@@ -372,3 +372,30 @@ def test_full_size_densify_properties(pms, hall_full):
     within = (rel[band & (gt > 0)] < 0.01).mean()
     print(f"full size: {within:.3f} of pixels within 1% of ground truth")
     assert within > 0.5
+
+
+@pytest.mark.parametrize("name", ["hall384", "box200"])
+def test_cost_does_not_depend_on_wave_mates(pms, name):
+    """Grazing planes at odd columns warp their patches far from the anchor
+    and push their waves onto the general angle form; the costs at the even
+    columns (untouched hypotheses) must come out bit for bit the same."""
+    w = _workload(name)
+    params = dict(w.params)
+    d, n = random_hypotheses(w, seed=41, gt_mix=0.8)
+    b = bearings(w.W, w.H).astype(np.float32)
+    rng = np.random.default_rng(42)
+    side = np.cross(b, rng.normal(size=3)[:, None, None], axis=0)
+    side /= np.linalg.norm(side, axis=0)
+    graze = (-0.02 * b + side).astype(np.float32)
+    graze /= np.linalg.norm(graze, axis=0)
+    d2, n2 = d.copy(), n.copy()
+    n2[:, :, 1::2] = graze[:, :, 1::2]
+    imgs = gpu_images(w)
+    ref, nbrs = split(w, imgs)
+    rp, nps = _poses(w)
+    say(f"wave-mate independence {name}")
+    c1 = pms.eval_cost(ref, nbrs, rp, nps, params, _t(d), _t(n)).cpu().numpy()
+    c2 = pms.eval_cost(ref, nbrs, rp, nps, params, _t(d2), _t(n2)).cpu().numpy()
+    assert np.array_equal(c1[:, 0::2], c2[:, 0::2])
+    # the grazing planes did change their own costs
+    assert not np.array_equal(c1[:, 1::2], c2[:, 1::2])
