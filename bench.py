@@ -12,6 +12,20 @@ neighbour against the other four keyframes of the window.
 A step is one full pms_densify call (reference statistics, random
 initialisation, 16 half-sweeps, output, consistency) with every input
 resident in HBM. Prints ONE JSON line on stdout; progress goes to stderr.
+
+Two more sections ride on the same line (skip them with --no-batch /
+--serve-horizon 0):
+* "batch": 32 keyframe jobs (12 at 960x480, 12 at 1920x960, 8 at
+  2880x1440, 3-6 neighbours each, hall generator and parameters) with
+  FP16 images, as one prepared batch replayed as one HIP graph launch under
+  the autotuned tile shape, against the plain FP32 path densifying the same
+  32 jobs one by one; accuracy of both against the rendered ground truth per
+  resolution class, and their agreement.
+* "serving": 8 streams of Poisson(3/s) requests of uniform width and 3-6
+  neighbours (FP16) through the continuous-batching server for
+  --serve-horizon seconds of arrivals: keyframes/s, p50/p99 latency from
+  arrival to result, mean batch occupancy; three served jobs re-run alone
+  must match bit for bit.
 """
 from __future__ import annotations
 
@@ -103,6 +117,145 @@ def cpu_baseline(w, params, budget_s: float, threads: int) -> dict:
                        f"x ({params['iterations']} iterations + 1/14 for the initialisation)")}
 
 
+def _gt_accuracy(depth, gt, r):
+    """Completeness (valid fraction of the band) and accuracy (fraction of
+    valid pixels within 1% of the ground-truth range) of one depth map."""
+    d = depth[r:depth.shape[0] - r]
+    g = gt[r:gt.shape[0] - r]
+    valid = d > 0
+    ok = valid & (g > 0) & (np.abs(d - g) <= 0.01 * np.maximum(g, 1e-9))
+    return float(valid.mean()), float(ok.sum() / max(valid.sum(), 1))
+
+
+def batch_section(args, torch, pms, synth, pool, ctx) -> dict:
+    """32 uneven FP16 jobs as one graph launch vs the plain FP32 path."""
+    dev = torch.device("cuda:0")
+    mix = synth.mixed_jobs({960: 12, 1920: 12, 2880: 8}, seed=args.seed)
+    # FP32 renders for the plain path, the same rounded to FP16 for the batch
+    imgs32 = {W: [torch.from_numpy(a).to(dev) for a in w.images] for W, w in pool.items()}
+    imgs16 = {W: [t.half() for t in ts] for W, ts in imgs32.items()}
+
+    def jobs_for(imgs):
+        out = []
+        for mj in mix:
+            w = pool[mj.W]
+            params = dict(w.params, seed=mj.seed)
+            out.append(pms.job(imgs[mj.W][mj.ref], [imgs[mj.W][k] for k in mj.nbrs],
+                               w.poses[mj.ref], [w.poses[k] for k in mj.nbrs], params))
+        return out
+
+    jobs16 = jobs_for(imgs16)
+    tune_ctx = pms.Context(0)
+    tune_set = [next(j for j, m in zip(jobs16, mix) if m.W == W) for W in (960, 1920, 2880)]
+    log("autotuning tile shapes on one job per width")
+    best, best_ms = tune_ctx.autotune(tune_set, reps=1)
+    log(f"autotuned schedule {best} ({best_ms:.1f} ms of init + half-sweeps)")
+    batch = pms.Batch(jobs16, ctx=tune_ctx)
+    log(f"batch of {len(jobs16)} jobs, {batch.nbytes / 2**30:.2f} GiB of device memory")
+    batch.run(graph=True)
+    torch.cuda.synchronize()
+    K = max(1, args.batch_reps)
+    t0 = time.perf_counter()
+    for _ in range(K):
+        batch.run(graph=True)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / K
+
+    # the plain FP32 form: the same jobs, FP32 images, one pms_densify each
+    jobs32 = jobs_for(imgs32)
+    for jd in jobs32[:2]:
+        pms.densify(jd.ref, jd.nbrs, jd.ref_pose, jd.nbr_poses, jd.params, out=jd.out, ctx=ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for jd in jobs32:
+        pms.densify(jd.ref, jd.nbrs, jd.ref_pose, jd.nbr_poses, jd.params, out=jd.out, ctx=ctx)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+
+    per_class = {}
+    for W in (960, 1920, 2880):
+        sel = [k for k, m in enumerate(mix) if m.W == W]
+        r = (pool[W].params["patch_size"] - 1) // 2
+        c16, a16, c32, a32, agree = [], [], [], [], []
+        for k in sel:
+            gt = pool[W].gt_depth[mix[k].ref]
+            d16 = jobs16[k].out[0].cpu().numpy()
+            d32 = jobs32[k].out[0].cpu().numpy()
+            c, a = _gt_accuracy(d16, gt, r)
+            c16.append(c)
+            a16.append(a)
+            c, a = _gt_accuracy(d32, gt, r)
+            c32.append(c)
+            a32.append(a)
+            both = (d16 > 0) & (d32 > 0)
+            agree.append(float((np.abs(d16[both] - d32[both]) <= 0.005 * d32[both]).mean()))
+        per_class[f"{W}x{W // 2}"] = {
+            "jobs": len(sel),
+            "fp16_batch": {"completeness": float(np.mean(c16)), "within_1pct_of_gt": float(np.mean(a16))},
+            "fp32_plain": {"completeness": float(np.mean(c32)), "within_1pct_of_gt": float(np.mean(a32))},
+            "fp16_vs_fp32_within_0.5pct": float(np.mean(agree)),
+        }
+    batch.close()
+    tune_ctx.close()
+    n = len(mix)
+    return {"workload": "32 jobs: 12@960x480, 12@1920x960, 8@2880x1440, N~U{3..6}",
+            "dtype": "f16 images, f32 accumulation",
+            "launch": "one HIP graph launch per batch",
+            "schedule": best,
+            "keyframes_per_s": n / t_batch, "s_per_batch": t_batch,
+            "plain_fp32_keyframes_per_s": n / t_plain, "plain_fp32_s": t_plain,
+            "speedup_vs_plain_fp32": t_plain / t_batch,
+            "accuracy_per_class": per_class}
+
+
+def serving_section(args, torch, pms, synth, pool, ctx) -> dict:
+    """Poisson request streams through the continuous-batching server."""
+    from paper_2211_16266_amd import serving
+    dev = torch.device("cuda:0")
+    imgs = {W: [torch.from_numpy(a).to(dev).half() for a in w.images] for W, w in pool.items()}
+    reqs = synth.poisson_requests(args.serve_streams, args.serve_rate, args.serve_horizon,
+                                  seed=args.seed + 7)
+
+    def factory(mj):
+        def make():
+            w = pool[mj.W]
+            params = dict(w.params, seed=mj.seed)
+            return pms.job(imgs[mj.W][mj.ref], [imgs[mj.W][k] for k in mj.nbrs], w.poses[mj.ref],
+                           [w.poses[k] for k in mj.nbrs], params)
+        return make
+
+    requests = [serving.Request(t, factory(mj), tag=(k, mj)) for k, (t, s, mj) in enumerate(reqs)]
+    server = pms.Server(int(args.serve_arena_gib * 2**30), max_jobs=args.serve_max_jobs,
+                        ctx=pms.Context(0))
+    check_tags = {0, len(requests) // 2, len(requests) - 1}
+    kept = {}
+
+    def on_done(rq, res):
+        if rq.tag[0] in check_tags:
+            kept[rq.tag[0]] = rq.job
+
+    log(f"serving {len(requests)} requests from {args.serve_streams} streams at "
+        f"{args.serve_rate}/s each over {args.serve_horizon:.0f} s")
+    out = serving.run(server, requests, on_done=on_done, log=log, keep_jobs=False)
+    torch.cuda.synchronize()
+    solo_equal = True
+    for k, jd in kept.items():
+        solo = pms.densify(jd.ref, jd.nbrs, jd.ref_pose, jd.nbr_poses, jd.params, ctx=server.ctx)
+        torch.cuda.synchronize()
+        solo_equal &= all(torch.equal(a, b) for a, b in zip(jd.out, solo))
+    server.close()
+    offered = args.serve_streams * args.serve_rate
+    return {"workload": f"{args.serve_streams} streams x Poisson({args.serve_rate}/s), widths "
+                        "960/1920/2880 uniform, N~U{3..6}, f16",
+            "horizon_s": args.serve_horizon, "requests": out["requests"],
+            "offered_keyframes_per_s": offered,
+            "keyframes_per_s": out["keyframes_per_s"], "wall_s": out["wall_s"],
+            "latency_ms": {"p50": out["p50_ms"], "p99": out["p99_ms"], "mean": out["mean_ms"]},
+            "mean_batch_occupancy": out["mean_occupancy"], "ticks": out["ticks"],
+            "max_jobs": args.serve_max_jobs, "arena_peak_gib": out["arena_peak_bytes"] / 2**30,
+            "solo_rerun_bitwise_equal": bool(solo_equal), "solo_rerun_checked": len(kept)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +264,14 @@ def main() -> int:
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-budget", type=float, default=12.0,
                     help="wall seconds of oracle work for the CPU baseline (0 = skip)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the mixed FP16 batch section")
+    ap.add_argument("--batch-reps", type=int, default=3)
+    ap.add_argument("--serve-horizon", type=float, default=20.0,
+                    help="seconds of request arrivals in the serving section (0 = skip)")
+    ap.add_argument("--serve-rate", type=float, default=3.0, help="arrivals per second per stream")
+    ap.add_argument("--serve-streams", type=int, default=8)
+    ap.add_argument("--serve-max-jobs", type=int, default=8)
+    ap.add_argument("--serve-arena-gib", type=float, default=16.0)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="bytes of a plain device-to-device copy run once before the "
                          "timed region, to calibrate HBM byte counters (0 = none)")
@@ -243,6 +404,14 @@ def main() -> int:
             "hbm_frac": hbm_bytes / avg_half_s / 1e9 / HBM_PEAK_GBS,
         },
     }
+    pool = None
+    if not args.no_batch or args.serve_horizon > 0:
+        log("rendering the mixed pool (7-keyframe hall windows at 960, 1920, 2880)")
+        pool = synth.mixed_pool(seed=args.seed, dtype="f32")
+    if not args.no_batch:
+        result["batch"] = batch_section(args, torch, pms, synth, pool, ctx)
+    if args.serve_horizon > 0:
+        result["serving"] = serving_section(args, torch, pms, synth, pool, ctx)
     if args.cpu_budget > 0:
         threads = min(os.cpu_count() or 1, 16)
         log(f"cpu baseline: oracle on {threads} threads, ~{args.cpu_budget:.0f} s")

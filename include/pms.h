@@ -68,6 +68,7 @@ typedef enum { PMS_F32 = 0, PMS_F16 = 1, PMS_U8 = 2 } pms_dtype;
 #define PMS_MAX_OFFSETS 16   /* propagation neighbourhood                  */
 #define PMS_MAX_SAMPLES 64   /* samples per patch                          */
 #define PMS_MAX_TRIALS 16    /* refinement trials per pixel and sweep      */
+#define PMS_MAX_BATCH 256    /* jobs per batch                             */
 
 typedef struct {
     const void *data;    /* device pointer                                 */
@@ -112,6 +113,39 @@ typedef struct {
 
 typedef struct pms_context pms_context;
 
+/* One keyframe densification job: the arguments of pms_densify gathered in
+   one struct (same meaning, same rules). The arrays it points to are host
+   memory read before the call that takes the job returns. */
+typedef struct {
+    pms_image ref;
+    pms_pose ref_pose;
+    const pms_image *nbrs;      /* n_nbrs images of ref's size and dtype     */
+    const pms_pose *nbr_poses;
+    int32_t n_nbrs;             /* 1 .. PMS_MAX_VIEWS                        */
+    const pms_plane *maps;      /* consistency maps; null when n_maps == 0   */
+    const pms_pose *map_poses;
+    int32_t n_maps;             /* 0 .. PMS_MAX_MAPS                         */
+    const pms_params *params;
+    pms_plane depth_out;
+    pms_plane normal_out[3];
+    pms_plane cost_out;
+} pms_job;
+
+/* Launch schedule of a context: the tile one 256-thread workgroup serves and
+   the lanes that share one pixel. A wave of 64 lanes holds 64 /
+   lanes_per_pixel pixels as wave_rows rows; a workgroup holds waves_x x
+   (4 / waves_x) waves. The tile shape never changes a result;
+   lanes_per_pixel (2 or 4; 2 is used for 36-sample patches only) changes
+   the order of the patch sums and therefore the last bits of the costs. */
+typedef struct {
+    int32_t wave_rows;       /* 1, 2, 4, 8 or 16; default 4 */
+    int32_t waves_x;         /* 1, 2 or 4; default 2        */
+    int32_t lanes_per_pixel; /* 2 or 4; default 4           */
+} pms_schedule;
+
+typedef struct pms_batch pms_batch;
+typedef struct pms_server pms_server;
+
 /* Defaults: 11x11 patch sampled every 2nd pixel, 8 iterations, 6 refinement
    trials (Sec. III-C, item 1), 0.3-30 m, the 8-neighbourhood of Sec. III-C
    with its inner ring moved out to distance 3 and the outer ring at 5, 1 px /
@@ -119,8 +153,10 @@ typedef struct pms_context pms_context;
 pms_status pms_default_params(pms_params *out);
 
 /* Creates a context on HIP device `device`. The context owns only scratch
-   memory (plane state, reference patch statistics, bearing tables), sized on
-   first use and never above scratch_budget_bytes (0 = no limit). device == -1
+   memory (plane state, reference patch statistics, re-laid-out neighbour
+   images, argument tables: one block sized on first use and grown when a
+   call needs more, never above scratch_budget_bytes, 0 = no limit; plus the
+   bearing tables of each image size it has seen). device == -1
    makes a validation-only context: every call checks its arguments as usual
    and then returns PMS_ERR_DEVICE instead of launching (no GPU needed). */
 pms_status pms_context_create(int32_t device, size_t scratch_budget_bytes, pms_context **out);
@@ -138,6 +174,76 @@ pms_status pms_densify(pms_context *ctx, const pms_image *ref, const pms_pose *r
                        const pms_plane *maps, const pms_pose *map_poses, int32_t n_maps,
                        const pms_params *params, pms_plane depth_out,
                        const pms_plane normal_out[3], pms_plane cost_out, void *stream);
+
+/* Densifies n_jobs (1 .. PMS_MAX_BATCH) keyframes of any mix of sizes,
+   neighbour counts and parameters together: every step of the method runs
+   as one launch over the tiles of all jobs still at that step, so small
+   keyframes share the GPU instead of under-filling it. Each job's outputs
+   are bitwise those of pms_densify on that job alone with the same context
+   schedule. No output plane may be shared by two jobs or be a consistency
+   map of the batch. Neighbour images that appear in several jobs (same
+   pointer, size, pitch and dtype) are re-laid out once. */
+pms_status pms_densify_batch(pms_context *ctx, const pms_job *jobs, int32_t n_jobs,
+                             void *stream);
+
+/* A batch prepared once and run many times: pms_batch_create validates the
+   jobs, allocates the batch's own device memory (plane state for every job,
+   re-laid-out images, argument tables) and uploads the tables; the images
+   and output planes are referenced, not copied, and must stay valid until
+   pms_batch_destroy (their contents may change between runs).
+   pms_batch_run only enqueues kernels on `stream`; with use_graph != 0 the
+   whole batch is captured into a HIP graph on its first run and every run
+   is one graph launch. pms_batch_destroy waits for the device. */
+pms_status pms_batch_create(pms_context *ctx, const pms_job *jobs, int32_t n_jobs,
+                            pms_batch **out);
+pms_status pms_batch_run(pms_batch *batch, int32_t use_graph, void *stream);
+pms_status pms_batch_bytes(const pms_batch *batch, size_t *bytes);
+pms_status pms_batch_destroy(pms_batch *batch);
+
+/* Schedule of a context (applies to every later call on it). */
+pms_status pms_get_schedule(const pms_context *ctx, pms_schedule *out);
+pms_status pms_set_schedule(pms_context *ctx, const pms_schedule *s);
+
+/* Autotuner: densifies the jobs (as one batch) under every tile shape (and,
+   with try_lanes != 0, both lanes_per_pixel values), timing the
+   initialisation and half-sweep kernels over `reps` runs after one warm-up,
+   and leaves the fastest schedule set on the context. Synchronous; the
+   jobs' output planes receive the last run's results. */
+pms_status pms_autotune(pms_context *ctx, const pms_job *jobs, int32_t n_jobs, int32_t reps,
+                        int32_t try_lanes, pms_schedule *best_out, double *best_ms_out,
+                        void *stream);
+
+/* Serving loop with continuous batching. A server owns one device arena of
+   arena_bytes (allocated once, at create) from which every admitted job
+   takes its plane state and the re-laid-out copies of its neighbour images
+   (shared, reference-counted, between jobs that name the same image).
+   pms_server_submit validates a job, copies its host-side description and
+   queues it (PMS_ERR_BUDGET if the job alone could never fit the arena);
+   its device buffers must stay valid, and its images unchanged, until the
+   job is done. Each pms_server_step is one tick on `stream`: waiting jobs
+   are admitted in submission order while their memory fits and fewer than
+   max_jobs run, then every running job advances by one half-sweep -- newly
+   admitted ones are laid out, get their patch statistics and random
+   initialisation first; the ones that complete their sweeps write their
+   outputs and run the consistency filter -- with one launch per step kind
+   and kernel variant over all jobs. A job's results are bitwise those of
+   pms_densify on it alone (same context schedule). At most two ticks are
+   in flight: a step waits for the tick before the previous one. Use one
+   stream per server; consistency maps must be final when their job is
+   submitted. */
+pms_status pms_server_create(pms_context *ctx, size_t arena_bytes, int32_t max_jobs,
+                             pms_server **out);
+pms_status pms_server_submit(pms_server *server, const pms_job *job, int64_t *ticket);
+pms_status pms_server_step(pms_server *server, void *stream, int32_t *active_out,
+                           int32_t *waiting_out);
+/* state: 0 waiting, 1 running (or enqueued but not finished on the device),
+   2 done -- reported once; the ticket is then forgotten. */
+pms_status pms_server_poll(pms_server *server, int64_t ticket, int32_t *state);
+/* Ticks run, the sum over ticks of running jobs (mean occupancy =
+   job_ticks / ticks), and the arena bytes in use now and at most. */
+pms_status pms_server_stats(const pms_server *server, int64_t *ticks, int64_t *job_ticks,
+                            size_t *arena_used, size_t *arena_peak);
+pms_status pms_server_destroy(pms_server *server);
 
 /* The matching cost alone (Sec. III-C: rectangular reference patch, any
    shape in the neighbours) for caller-given hypotheses: cost_out receives the
@@ -176,8 +282,9 @@ pms_status pms_philox_stream(pms_context *ctx, uint64_t key0, uint64_t key1, uin
 /* Per-kernel timing with HIP events around each launch (off by default).
    pms_profile_read synchronises on the recorded events, returns the launch
    count and total milliseconds of kernel `name` ("halfsweep", "init",
-   "refstats", "finalize", "consistency", "eval") since the last read, and
-   clears them. */
+   "refstats", "finalize", "consistency", "eval", "io" for the image
+   re-layout and state copies, "batch" for whole graph launches) since the
+   last read, and clears them. A graph launch is timed as one "batch". */
 pms_status pms_profile_enable(pms_context *ctx, int32_t on);
 pms_status pms_profile_read(pms_context *ctx, const char *name, int64_t *launches,
                             double *total_ms);

@@ -11,6 +11,6 @@ The work runs in the HIP kernels of ``libpms.so`` behind the C ABI of
 """
 import torch  # noqa: F401  (load torch's HIP runtime before libpms)
 
-from ._binding import (LIB_PATH, MAX_MAPS, MAX_VIEWS, Context, PmsError, consistency,  # noqa: F401
-                       default_context, default_params, densify, eval_cost, halfsweep, lib,
-                       philox_stream)
+from ._binding import (LIB_PATH, MAX_BATCH, MAX_MAPS, MAX_VIEWS, Batch, Context,  # noqa: F401
+                       JobDesc, PmsError, Server, consistency, default_context, default_params, densify,
+                       densify_batch, eval_cost, halfsweep, job, lib, philox_stream)

@@ -45,6 +45,9 @@ class Pose(C.Structure):
     _fields_ = [("R", C.c_double * 9), ("t", C.c_double * 3)]
 
 
+MAX_BATCH = 256
+
+
 class Params(C.Structure):
     _fields_ = [
         ("patch_size", C.c_int32), ("patch_stride", C.c_int32), ("iterations", C.c_int32),
@@ -56,6 +59,18 @@ class Params(C.Structure):
         ("geo_px", C.c_double), ("geo_rel_depth", C.c_double), ("geo_min_views", C.c_int32),
         ("seed", C.c_uint64),
     ]
+
+
+class Job(C.Structure):
+    _fields_ = [("ref", Image), ("ref_pose", Pose), ("nbrs", C.POINTER(Image)),
+                ("nbr_poses", C.POINTER(Pose)), ("n_nbrs", C.c_int32),
+                ("maps", C.POINTER(Plane)), ("map_poses", C.POINTER(Pose)), ("n_maps", C.c_int32),
+                ("params", C.POINTER(Params)), ("depth_out", Plane), ("normal_out", Plane * 3),
+                ("cost_out", Plane)]
+
+
+class Schedule(C.Structure):
+    _fields_ = [("wave_rows", C.c_int32), ("waves_x", C.c_int32), ("lanes_per_pixel", C.c_int32)]
 
 
 _lib = None
@@ -87,13 +102,33 @@ def lib() -> C.CDLL:
                                         C.c_void_p, C.c_void_p]
         L.pms_profile_enable.argtypes = [C.c_void_p, C.c_int32]
         L.pms_profile_read.argtypes = [C.c_void_p, C.c_char_p, P(C.c_int64), P(C.c_double)]
+        L.pms_densify_batch.argtypes = [C.c_void_p, P(Job), C.c_int32, C.c_void_p]
+        L.pms_batch_create.argtypes = [C.c_void_p, P(Job), C.c_int32, P(C.c_void_p)]
+        L.pms_batch_run.argtypes = [C.c_void_p, C.c_int32, C.c_void_p]
+        L.pms_batch_bytes.argtypes = [C.c_void_p, P(C.c_size_t)]
+        L.pms_batch_destroy.argtypes = [C.c_void_p]
+        L.pms_get_schedule.argtypes = [C.c_void_p, P(Schedule)]
+        L.pms_set_schedule.argtypes = [C.c_void_p, P(Schedule)]
+        L.pms_autotune.argtypes = [C.c_void_p, P(Job), C.c_int32, C.c_int32, C.c_int32,
+                                   P(Schedule), P(C.c_double), C.c_void_p]
+        L.pms_server_create.argtypes = [C.c_void_p, C.c_size_t, C.c_int32, P(C.c_void_p)]
+        L.pms_server_submit.argtypes = [C.c_void_p, P(Job), P(C.c_int64)]
+        L.pms_server_step.argtypes = [C.c_void_p, C.c_void_p, P(C.c_int32), P(C.c_int32)]
+        L.pms_server_poll.argtypes = [C.c_void_p, C.c_int64, P(C.c_int32)]
+        L.pms_server_stats.argtypes = [C.c_void_p, P(C.c_int64), P(C.c_int64), P(C.c_size_t),
+                                       P(C.c_size_t)]
+        L.pms_server_destroy.argtypes = [C.c_void_p]
         L.pms_status_string.argtypes = [C.c_int]
         L.pms_status_string.restype = C.c_char_p
         L.pms_last_error.argtypes = [C.c_void_p]
         L.pms_last_error.restype = C.c_char_p
         for name in ("pms_default_params", "pms_context_create", "pms_context_destroy",
                      "pms_densify", "pms_eval_cost", "pms_halfsweep", "pms_consistency",
-                     "pms_philox_stream", "pms_profile_enable", "pms_profile_read"):
+                     "pms_philox_stream", "pms_profile_enable", "pms_profile_read",
+                     "pms_densify_batch", "pms_batch_create", "pms_batch_run", "pms_batch_bytes",
+                     "pms_batch_destroy", "pms_get_schedule", "pms_set_schedule", "pms_autotune",
+                     "pms_server_create", "pms_server_submit", "pms_server_step",
+                     "pms_server_poll", "pms_server_stats", "pms_server_destroy"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -215,6 +250,29 @@ class Context:
     def profile_enable(self, on: bool = True) -> None:
         self.check(lib().pms_profile_enable(self.handle, int(bool(on))), "pms_profile_enable")
 
+    def get_schedule(self) -> dict:
+        sc = Schedule()
+        self.check(lib().pms_get_schedule(self.handle, C.byref(sc)), "pms_get_schedule")
+        return {"wave_rows": sc.wave_rows, "waves_x": sc.waves_x,
+                "lanes_per_pixel": sc.lanes_per_pixel}
+
+    def set_schedule(self, wave_rows: int = 4, waves_x: int = 2, lanes_per_pixel: int = 4) -> None:
+        sc = Schedule(int(wave_rows), int(waves_x), int(lanes_per_pixel))
+        self.check(lib().pms_set_schedule(self.handle, C.byref(sc)), "pms_set_schedule")
+
+    def autotune(self, jobs, reps: int = 2, try_lanes: bool = False, stream=None) -> tuple[dict, float]:
+        """Times every tile shape on ``jobs`` (see ``job``) and keeps the
+        fastest; returns (schedule, milliseconds of init + half-sweeps)."""
+        arr, keep = _job_array(jobs)
+        sc = Schedule()
+        ms = C.c_double()
+        self.check(lib().pms_autotune(self.handle, arr, len(jobs), int(reps), int(bool(try_lanes)),
+                                      C.byref(sc), C.byref(ms), C.c_void_p(_stream_handle(stream))),
+                   "pms_autotune")
+        del keep
+        return ({"wave_rows": sc.wave_rows, "waves_x": sc.waves_x,
+                 "lanes_per_pixel": sc.lanes_per_pixel}, ms.value)
+
     def profile_read(self, name: str) -> tuple[int, float]:
         n = C.c_int64()
         ms = C.c_double()
@@ -321,3 +379,169 @@ def philox_stream(key0: int, key1: int, ctr0: int, n: int, device: int = 0,
                                  C.c_void_p(out.data_ptr()), C.c_void_p(_stream_handle(stream)))
     ctx.check(st, "pms_philox_stream")
     return out
+
+
+# ----------------------------------------------------------------------------
+# batches
+# ----------------------------------------------------------------------------
+
+class JobDesc:
+    """One keyframe job for the batch calls: the arguments of ``densify``.
+    ``out`` = (depth, normal, cost) tensors; allocated when omitted."""
+
+    def __init__(self, ref, nbrs, ref_pose, nbr_poses, params=None, maps=None, map_poses=None,
+                 out=None):
+        self.ref, self.nbrs = ref, list(nbrs)
+        self.ref_pose, self.nbr_poses = ref_pose, list(nbr_poses)
+        self.params = params
+        self.maps, self.map_poses = list(maps or []), list(map_poses or [])
+        if len(self.maps) != len(self.map_poses):
+            raise ValueError("maps and map_poses differ in length")
+        if len(self.nbrs) != len(self.nbr_poses):
+            raise ValueError("nbrs and nbr_poses differ in length")
+        if out is None:
+            H, W = ref.shape
+            out = (torch.empty((H, W), dtype=torch.float32, device=ref.device),
+                   torch.empty((3, H, W), dtype=torch.float32, device=ref.device),
+                   torch.empty((H, W), dtype=torch.float32, device=ref.device))
+        self.out = out
+
+
+def job(ref, nbrs, ref_pose, nbr_poses, params=None, maps=None, map_poses=None, out=None) -> JobDesc:
+    return JobDesc(ref, nbrs, ref_pose, nbr_poses, params, maps, map_poses, out)
+
+
+def _job_array(jobs):
+    if not 1 <= len(jobs) <= MAX_BATCH:
+        raise ValueError(f"a batch holds 1 to {MAX_BATCH} jobs")
+    arr = (Job * len(jobs))()
+    keep = []
+    for i, jd in enumerate(jobs):
+        nb = _views(jd.nbrs)
+        npz = _poses(jd.nbr_poses)
+        mp = (Plane * max(1, len(jd.maps)))(*[make_plane(m, "map") for m in jd.maps])
+        mpz = _poses(jd.map_poses)
+        prm = make_params(jd.params)
+        depth, normal, cost = jd.out
+        arr[i].ref = make_image(jd.ref, "ref")
+        arr[i].ref_pose = make_pose(jd.ref_pose)
+        arr[i].nbrs = C.cast(nb, C.POINTER(Image))
+        arr[i].nbr_poses = C.cast(npz, C.POINTER(Pose))
+        arr[i].n_nbrs = len(jd.nbrs)
+        arr[i].maps = C.cast(mp, C.POINTER(Plane)) if jd.maps else None
+        arr[i].map_poses = C.cast(mpz, C.POINTER(Pose)) if jd.maps else None
+        arr[i].n_maps = len(jd.maps)
+        arr[i].params = C.pointer(prm)
+        arr[i].depth_out = make_plane(depth, "depth")
+        for k in range(3):
+            arr[i].normal_out[k] = make_plane(normal[k], "normal")
+        arr[i].cost_out = make_plane(cost, "cost")
+        keep += [nb, npz, mp, mpz, prm]
+    return arr, keep
+
+
+def densify_batch(jobs, ctx: Context | None = None, stream=None):
+    """Densifies every ``JobDesc`` in one batch; returns their ``out``."""
+    ctx = ctx or default_context(jobs[0].ref.device.index or 0)
+    arr, keep = _job_array(jobs)
+    ctx.check(lib().pms_densify_batch(ctx.handle, arr, len(jobs),
+                                      C.c_void_p(_stream_handle(stream))), "pms_densify_batch")
+    del keep
+    return [jd.out for jd in jobs]
+
+
+class Batch:
+    """A prepared batch (pms_batch_*): device memory and argument tables are
+    set up once; ``run`` enqueues the whole batch, as one HIP graph launch
+    when ``graph`` is set. The jobs' tensors must outlive the batch."""
+
+    def __init__(self, jobs, ctx: Context | None = None):
+        self.ctx = ctx or default_context(jobs[0].ref.device.index or 0)
+        self.jobs = list(jobs)
+        arr, keep = _job_array(self.jobs)
+        h = C.c_void_p()
+        self.ctx.check(lib().pms_batch_create(self.ctx.handle, arr, len(jobs), C.byref(h)),
+                       "pms_batch_create")
+        del keep
+        self.handle = h
+
+    def run(self, graph: bool = True, stream=None) -> None:
+        self.ctx.check(lib().pms_batch_run(self.handle, int(bool(graph)),
+                                           C.c_void_p(_stream_handle(stream))), "pms_batch_run")
+
+    @property
+    def nbytes(self) -> int:
+        n = C.c_size_t()
+        self.ctx.check(lib().pms_batch_bytes(self.handle, C.byref(n)), "pms_batch_bytes")
+        return n.value
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            lib().pms_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching server (pms_server_*): jobs are submitted as they
+    arrive and advance one half-sweep per ``step`` together with every other
+    admitted job. ``poll`` reports a ticket's state once it is done; the
+    job's tensors must stay alive until then."""
+
+    WAITING, RUNNING, DONE = 0, 1, 2
+
+    def __init__(self, arena_bytes: int, max_jobs: int = 64, ctx: Context | None = None):
+        self.ctx = ctx or default_context(0)
+        h = C.c_void_p()
+        self.ctx.check(lib().pms_server_create(self.ctx.handle, int(arena_bytes), int(max_jobs),
+                                               C.byref(h)), "pms_server_create")
+        self.handle = h
+        self._jobs = {}
+
+    def submit(self, jd: JobDesc) -> int:
+        arr, keep = _job_array([jd])
+        t = C.c_int64()
+        self.ctx.check(lib().pms_server_submit(self.handle, arr, C.byref(t)), "pms_server_submit")
+        del keep
+        self._jobs[t.value] = jd  # keeps the tensors alive
+        return t.value
+
+    def step(self, stream=None) -> tuple[int, int]:
+        a = C.c_int32()
+        w = C.c_int32()
+        self.ctx.check(lib().pms_server_step(self.handle, C.c_void_p(_stream_handle(stream)),
+                                             C.byref(a), C.byref(w)), "pms_server_step")
+        return a.value, w.value
+
+    def poll(self, ticket: int) -> int:
+        st = C.c_int32()
+        self.ctx.check(lib().pms_server_poll(self.handle, int(ticket), C.byref(st)), "pms_server_poll")
+        if st.value == self.DONE:
+            self._jobs.pop(ticket, None)
+        return st.value
+
+    def stats(self) -> dict:
+        t, jt = C.c_int64(), C.c_int64()
+        used, peak = C.c_size_t(), C.c_size_t()
+        self.ctx.check(lib().pms_server_stats(self.handle, C.byref(t), C.byref(jt), C.byref(used),
+                                              C.byref(peak)), "pms_server_stats")
+        return {"ticks": t.value, "job_ticks": jt.value, "arena_used": used.value,
+                "arena_peak": peak.value,
+                "mean_occupancy": jt.value / t.value if t.value else 0.0}
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            lib().pms_server_destroy(self.handle)
+            self.handle = None
+            self._jobs.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,29 +1,66 @@
 // pms.hip -- host side of libpms: argument validation, FP64 pose
-// composition, scratch management and kernel launches behind the C ABI
-// declared in include/pms.h.
+// composition, device memory and the launch plans behind the C ABI declared
+// in include/pms.h.
+//
+// Every computation is described as a plan: a table of per-job kernel
+// arguments (JobArgs), per-launch entry lists naming which job (and, for a
+// half-sweep, which iteration and colour) each range of workgroups serves,
+// and the ordered list of launches. One keyframe (pms_densify), a batch of
+// uneven keyframes (pms_densify_batch, pms_batch_*) and the serving loop's
+// ticks (pms_server_*) all run through the same kernels; a pixel's
+// arithmetic does not depend on which other jobs share its launch or on the
+// tile shape.
 #include "pms.h"
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
+#include <tuple>
+#include <utility>
 #include <vector>
 
 #include "pms_kernels.hpp"
 
 namespace {
 
-constexpr int kNumKernelKinds = 7;
+constexpr int kNumKernelKinds = 8;
 const char *const kKernelNames[kNumKernelKinds] = {"refstats", "init", "halfsweep", "finalize",
-                                                   "consistency", "eval", "io"};
-enum KernelKind { KK_REFSTATS, KK_INIT, KK_HALFSWEEP, KK_FINALIZE, KK_CONSISTENCY, KK_EVAL, KK_IO };
+                                                   "consistency", "eval", "io", "batch"};
+enum KernelKind {
+    KK_REFSTATS, KK_INIT, KK_HALFSWEEP, KK_FINALIZE, KK_CONSISTENCY, KK_EVAL, KK_IO, KK_GRAPH
+};
 
 struct TimedLaunch {
     int kind;
     hipEvent_t start, stop;
+};
+
+// Bearing tables of one image size, built once per context and size.
+struct Tables {
+    float2 *row = nullptr, *col = nullptr;
+    double2 *row64 = nullptr, *col64 = nullptr;
+};
+
+// Pinned host buffers for argument uploads, reused in turn; a buffer is
+// rewritten only after the copy that last read it has run.
+constexpr int kStagingSlots = 4;
+struct Staging {
+    void *host = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+};
+
+// Tile shape and patch schedule used by every launch of a context.
+struct Schedule {
+    int wy_log2 = 2;  // a wave covers 2^wy_log2 pixel rows
+    int bx_log2 = 1;  // a workgroup holds 2^bx_log2 waves side by side
+    int lpp = 0;      // lanes per pixel for 36-sample patches (0: 4)
 };
 
 }  // namespace
@@ -31,22 +68,16 @@ struct TimedLaunch {
 struct pms_context {
     int device = 0;
     size_t budget = 0;
-    // scratch: [state float4 | cost float | stats float2] for `cap_pixels`
-    // pixels, then the bearing tables for (tab_W, tab_H)
-    void *scratch = nullptr;
-    size_t scratch_bytes = 0;
-    long long cap_pixels = 0;
-    float4 *state = nullptr;
-    float *cost = nullptr;
-    float2 *stats = nullptr;
-    float2 *tab_row = nullptr;
-    float2 *tab_col = nullptr;
-    double2 *tab_row64 = nullptr;
-    double2 *tab_col64 = nullptr;
-    int tab_W = 0, tab_H = 0;
-    void *pad[pms::MAXV] = {};  // re-laid-out neighbour images
-    int pad_Wp = 0;
-    int pad_bytes = 0;
+    // device block of the calls that run one plan at a time: argument
+    // tables first, then per-job plane state and re-laid-out images
+    void *work = nullptr;
+    size_t work_bytes = 0;
+    std::map<std::pair<int, int>, Tables> tables;
+    Staging staging[kStagingSlots];
+    int staging_next = 0;
+    Schedule sched;
+    hipStream_t capture_stream = nullptr;
+    bool capturing = false;
     std::string last_error;
     bool profiling = false;
     std::vector<TimedLaunch> launches;
@@ -240,74 +271,60 @@ pms::ViewPoseF relative_pose(const pms_pose &ref, const pms_pose &nbr)
     return out;
 }
 
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
 size_t pad_elem_size(int dtype) { return dtype == PMS_F16 ? 2 : 4; }
 
-// Grows the scratch block to hold W x H pixels of state, the bearing tables
-// and n_pad re-laid-out neighbour images of `pad_elem` bytes per value.
-pms_status ensure_scratch(pms_context *ctx, int W, int H, int n_pad, size_t pad_elem,
-                          hipStream_t stream)
+pms_status set_device(pms_context *ctx)
 {
-    const long long npx = (long long)W * H;
-    const size_t state_b = (size_t)npx * sizeof(float4);
-    const size_t cost_b = (size_t)npx * sizeof(float);
-    const size_t stats_b = (size_t)npx * sizeof(float2);
-    const size_t tabs_b = (size_t)(W + H) * (sizeof(float2) + sizeof(double2));
-    const int Wp = 2 * W + 4;
-    const size_t pad_b = (size_t)(H + 2) * Wp * pad_elem;
-    auto align = [](size_t v) { return (v + 255) & ~(size_t)255; };
-    const size_t need = align(state_b) + align(cost_b) + align(stats_b) + align(tabs_b) +
-                        (size_t)n_pad * align(pad_b);
     if (ctx->device < 0) return fail(ctx, PMS_ERR_DEVICE, "validation-only context cannot launch");
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
-    if (need > ctx->scratch_bytes) {
-        if (ctx->budget && need > ctx->budget)
-            return fail(ctx, PMS_ERR_BUDGET, "scratch for this image size exceeds the context budget");
-        if (ctx->scratch) {
-            // earlier work may still use the old block
-            e = hipDeviceSynchronize();
-            if (e != hipSuccess) return hip_fail(ctx, e, "hipDeviceSynchronize");
-            (void)hipFree(ctx->scratch);
-            ctx->scratch = nullptr;
-            ctx->scratch_bytes = 0;
-        }
-        e = hipMalloc(&ctx->scratch, need);
-        if (e != hipSuccess) {
-            ctx->scratch = nullptr;
-            return fail(ctx, PMS_ERR_OUT_OF_MEMORY, "hipMalloc of scratch failed");
-        }
-        ctx->scratch_bytes = need;
-        ctx->tab_W = ctx->tab_H = 0;
+    return PMS_OK;
+}
+
+// Bearing tables of a W x H image (per row sin/cos of the latitude, per
+// column sin/cos of the longitude, FP64 and rounded to FP32), computed on
+// the host once per size and kept for the context's lifetime.
+pms_status get_tables(pms_context *ctx, int W, int H, Tables *out)
+{
+    auto it = ctx->tables.find({W, H});
+    if (it != ctx->tables.end()) {
+        *out = it->second;
+        return PMS_OK;
     }
-    char *base = static_cast<char *>(ctx->scratch);
-    ctx->state = reinterpret_cast<float4 *>(base);
-    base += align(state_b);
-    ctx->cost = reinterpret_cast<float *>(base);
-    base += align(cost_b);
-    ctx->stats = reinterpret_cast<float2 *>(base);
-    base += align(stats_b);
-    float2 *tabs = reinterpret_cast<float2 *>(base);
-    base += align(tabs_b);
-    for (int j = 0; j < pms::MAXV; ++j) {
-        ctx->pad[j] = j < n_pad ? static_cast<void *>(base) : nullptr;
-        if (j < n_pad) base += align(pad_b);
+    const size_t n = (size_t)W + H;
+    std::vector<char> host(n * (sizeof(float2) + sizeof(double2)));
+    float2 *row = reinterpret_cast<float2 *>(host.data());
+    float2 *col = row + H;
+    double2 *row64 = reinterpret_cast<double2 *>(row + n);
+    double2 *col64 = row64 + H;
+    const double PI = 3.14159265358979323846;
+    for (int i = 0; i < H; ++i) {
+        const double phi = PI / 2.0 - PI * (i + 0.5) / H;
+        row64[i] = make_double2(std::sin(phi), std::cos(phi));
+        row[i] = make_float2((float)row64[i].x, (float)row64[i].y);
     }
-    ctx->pad_Wp = Wp;
-    ctx->pad_bytes = (int)pad_b;
-    if (ctx->tab_W != W || ctx->tab_H != H || ctx->tab_row != tabs) {
-        ctx->tab_row = tabs;
-        ctx->tab_col = tabs + H;
-        ctx->tab_row64 = reinterpret_cast<double2 *>(tabs + W + H);
-        ctx->tab_col64 = ctx->tab_row64 + H;
-        const int n = W > H ? W : H;
-        hipLaunchKernelGGL(pms::k_tables, dim3((n + 255) / 256), dim3(256), 0, stream, W, H,
-                           ctx->tab_row, ctx->tab_col, ctx->tab_row64, ctx->tab_col64);
-        e = hipGetLastError();
-        if (e != hipSuccess) return hip_fail(ctx, e, "k_tables launch");
-        ctx->tab_W = W;
-        ctx->tab_H = H;
+    for (int i = 0; i < W; ++i) {
+        const double lam = 2.0 * PI * (i + 0.5) / W - PI;
+        col64[i] = make_double2(std::sin(lam), std::cos(lam));
+        col[i] = make_float2((float)col64[i].x, (float)col64[i].y);
     }
-    ctx->cap_pixels = npx;
+    void *dev = nullptr;
+    hipError_t e = hipMalloc(&dev, host.size());
+    if (e != hipSuccess) return fail(ctx, PMS_ERR_OUT_OF_MEMORY, "hipMalloc of bearing tables failed");
+    e = hipMemcpy(dev, host.data(), host.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(dev);
+        return hip_fail(ctx, e, "bearing table upload");
+    }
+    Tables t;
+    t.row = static_cast<float2 *>(dev);
+    t.col = t.row + H;
+    t.row64 = reinterpret_cast<double2 *>(t.row + n);
+    t.col64 = t.row64 + H;
+    ctx->tables[{W, H}] = t;
+    *out = t;
     return PMS_OK;
 }
 
@@ -330,7 +347,7 @@ struct LaunchTimer {
     hipEvent_t a = nullptr, b = nullptr;
     LaunchTimer(pms_context *c, int k, hipStream_t s) : ctx(c), kind(k), stream(s)
     {
-        if (ctx->profiling) {
+        if (ctx->profiling && !ctx->capturing) {
             a = take_event(ctx);
             b = take_event(ctx);
             if (a) (void)hipEventRecord(a, stream);
@@ -338,28 +355,153 @@ struct LaunchTimer {
     }
     ~LaunchTimer()
     {
-        if (ctx->profiling && a && b) {
+        if (a && b) {
             (void)hipEventRecord(b, stream);
             ctx->launches.push_back({kind, a, b});
         }
     }
 };
 
-void fill_common(pms::SweepArgs &A, const pms_context *ctx, const pms_image *ref,
-                 const pms_pose *ref_pose, const pms_image *nbrs, const pms_pose *nbr_poses,
-                 int n_nbrs, const pms_params *p)
+// Lanes per pixel, samples per lane, and whether every lane owns exactly
+// that many samples: a function of the patch size and the context's
+// schedule, never of the launch.
+struct Variant {
+    int lpp, spl;
+    bool full;
+};
+
+Variant pick_variant(int P, const Schedule &sc)
 {
-    std::memset(&A, 0, sizeof A);
-    const int W = ref->width, H = ref->height;
+    if (P == 36 && sc.lpp == 2) return {2, 18, true};
+    if (P % 4 == 0 && (P / 4 == 9 || P / 4 == 16)) return {4, P / 4, true};
+    const int need = (P + 3) / 4;
+    return {4, need <= 4 ? 4 : need <= 9 ? 9 : need <= 13 ? 13 : 16, false};
+}
+
+int ilog2(int v)
+{
+    int l = 0;
+    while ((1 << (l + 1)) <= v) ++l;
+    return l;
+}
+
+enum Mode { MODE_DENSIFY, MODE_EVAL, MODE_SWEEP, MODE_GEO };
+
+// One validated job of a plan.
+struct JobSpec {
+    int mode = MODE_DENSIFY;
+    int W = 0, H = 0;
+    const pms_image *ref = nullptr;
+    const pms_pose *ref_pose = nullptr;
+    const pms_image *nbrs = nullptr;
+    const pms_pose *nbr_poses = nullptr;
+    int n_nbrs = 0;
+    const pms_plane *maps = nullptr;
+    const pms_pose *map_poses = nullptr;
+    int n_maps = 0;
+    const pms_params *p = nullptr;
+    pms_plane depth{}, normal[3]{}, cost{};  // outputs, or in/out planes
+    pms_plane depth_in{}, normal_in[3]{};    // MODE_EVAL hypotheses
+    const pms_plane *per_view = nullptr;     // MODE_EVAL, nullable
+    int iteration = 0, colour = 0;           // MODE_SWEEP
+};
+
+// Tile geometry of one job under a schedule.
+struct Geometry {
+    Variant v;
+    int r, wx_log2, wy_log2, bx_log2, tile_w, tile_h;
+    int tiles_x_all, tiles_y_all, tiles_x_half, tiles_y_half;
+};
+
+Geometry geometry(const JobSpec &J, const Schedule &sc)
+{
+    Geometry g;
+    g.v = pick_variant(patch_samples(*J.p), sc);
+    g.r = (J.p->patch_size - 1) / 2;
+    const int pix_log2 = ilog2(64 / g.v.lpp);  // pixels per wave
+    g.wy_log2 = std::min(sc.wy_log2, pix_log2);
+    g.wx_log2 = pix_log2 - g.wy_log2;
+    g.bx_log2 = sc.bx_log2;
+    g.tile_w = (1 << g.wx_log2) << g.bx_log2;
+    g.tile_h = (1 << g.wy_log2) * (4 >> g.bx_log2);
+    g.tiles_x_all = (J.W + g.tile_w - 1) / g.tile_w;
+    g.tiles_y_all = (J.H + g.tile_h - 1) / g.tile_h;
+    const int rows = J.H - 2 * g.r;
+    g.tiles_x_half = (J.W / 2 + g.tile_w - 1) / g.tile_w;
+    g.tiles_y_half = rows > 0 ? (rows + g.tile_h - 1) / g.tile_h : 0;
+    return g;
+}
+
+// A launch of a plan: kernel kind, the entry list it walks, and for the
+// state hooks the job they copy.
+enum IoSub { IO_PAD = 0, IO_LOAD = 1, IO_STORE = 2 };
+struct Rec {
+    int kind;
+    int sub;
+    int dtype;
+    Variant v;
+    size_t entry_off;
+    int n_entries;
+    int total;
+    int job, colour;
+};
+
+struct Plan {
+    std::vector<pms::JobArgs> jobs;
+    std::vector<pms::PadJob> pads;
+    std::vector<pms::Entry> entries;
+    std::vector<Rec> recs;
+    size_t off_pads = 0, off_entries = 0, args_bytes = 0, total_bytes = 0;
+};
+
+// Appends a launch over (job, blocks, iteration, colour) items.
+void add_rec(Plan &P, int kind, int sub, int dtype, Variant v,
+             const std::vector<std::tuple<int, int, int, int>> &items)
+{
+    Rec R{};
+    R.kind = kind;
+    R.sub = sub;
+    R.dtype = dtype;
+    R.v = v;
+    R.entry_off = P.entries.size();
+    int first = 0;
+    for (auto &it : items) {
+        const int blocks = std::get<1>(it);
+        if (blocks <= 0) continue;
+        P.entries.push_back({std::get<0>(it), first, std::get<2>(it), std::get<3>(it)});
+        first += blocks;
+    }
+    R.n_entries = (int)(P.entries.size() - R.entry_off);
+    if (R.n_entries == 0) {
+        P.entries.resize(R.entry_off);
+        return;
+    }
+    P.entries.push_back({-1, first, 0, 0});
+    R.total = first;
+    P.recs.push_back(R);
+}
+
+long long blocks_of(long long n) { return (n + pms::BLOCK - 1) / pms::BLOCK; }
+
+using GroupKey = std::tuple<int, int, int, int>;  // dtype, lpp, spl, full
+GroupKey group_key(const JobSpec &J, const Geometry &g)
+{
+    return GroupKey(J.ref->dtype, g.v.lpp, g.v.spl, g.v.full ? 1 : 0);
+}
+
+void fill_sweep_args(pms::SweepArgs &A, const JobSpec &J, const Geometry &g, const Tables &T)
+{
+    const pms_params *p = J.p;
+    const int W = J.W, H = J.H;
     A.W = W;
     A.H = H;
-    A.r = (p->patch_size - 1) / 2;
+    A.r = g.r;
     A.stride = p->patch_stride;
     A.side = 2 * A.r / A.stride + 1;
     A.P = A.side * A.side;
     A.inv_P = (float)(1.0 / A.P);
-    A.n_views = n_nbrs;
-    A.top_k = p->top_k > 0 ? p->top_k : (n_nbrs + 1) / 2;
+    A.n_views = J.n_nbrs;
+    A.top_k = p->top_k > 0 ? p->top_k : (J.n_nbrs + 1) / 2;
     A.k_float = (float)A.top_k;
     A.var_floor = (float)p->ncc_var_floor;
     A.dmin = (float)p->depth_min;
@@ -387,158 +529,388 @@ void fill_common(pms::SweepArgs &A, const pms_context *ctx, const pms_image *ref
         A.sn[k] = (float)(p->refine_sigma_normal0 * std::pow(p->refine_normal_shrink, k));
     }
     A.seed = p->seed;
-    A.ref.ptr = ref->data;
-    A.ref.pitch = ref->pitch_bytes;
-    for (int j = 0; j < n_nbrs; ++j) {
-        A.pad[j] = ctx->pad[j];
-        A.pose[j] = relative_pose64(*ref_pose, nbr_poses[j]);
-        A.posef[j] = relative_pose(*ref_pose, nbr_poses[j]);
+    A.wx_log2 = g.wx_log2;
+    A.bx_log2 = g.bx_log2;
+    A.tile_w = g.tile_w;
+    A.tile_h = g.tile_h;
+    A.tiles_x_all = g.tiles_x_all;
+    A.tiles_x_half = g.tiles_x_half;
+    A.ref_dtype = J.ref->dtype;
+    A.ref.ptr = J.ref->data;
+    A.ref.pitch = J.ref->pitch_bytes;
+    for (int j = 0; j < J.n_nbrs; ++j) {
+        A.pose[j] = relative_pose64(*J.ref_pose, J.nbr_poses[j]);
+        A.posef[j] = relative_pose(*J.ref_pose, J.nbr_poses[j]);
     }
-    A.Wp = ctx->pad_Wp;
-    A.pad_bytes = ctx->pad_bytes;
-    A.tab_row = ctx->tab_row;
-    A.tab_col = ctx->tab_col;
-    A.tab_row64 = ctx->tab_row64;
-    A.tab_col64 = ctx->tab_col64;
-    A.stats = ctx->stats;
-    A.state = ctx->state;
-    A.cost = ctx->cost;
+    A.Wp = 2 * W + 4;
+    A.pad_bytes = (int)((size_t)(H + 2) * A.Wp * pad_elem_size(J.ref->dtype));
+    A.tab_row = T.row;
+    A.tab_col = T.col;
+    A.tab_row64 = T.row64;
+    A.tab_col64 = T.col64;
 }
 
-// Lanes per pixel, samples per lane, and whether every lane owns exactly
-// that many samples: a function of the patch size alone, so results never
-// depend on launch shapes.
-struct Variant {
-    int lpp, spl;
-    bool full;
-};
-
-#ifndef PMS_P36_LPP
-#define PMS_P36_LPP 4
-#endif
-
-Variant pick_variant(int P)
+void fill_io(pms::IoArgs &io, const JobSpec &J, int r, float4 *state, float *cost)
 {
-    if (P == 36 && PMS_P36_LPP == 2) return {2, 18, true};
-    if (P % 4 == 0 && (P / 4 == 9 || P / 4 == 16)) return {4, P / 4, true};
-    const int need = (P + 3) / 4;
-    return {4, need <= 4 ? 4 : need <= 9 ? 9 : need <= 13 ? 13 : 16, false};
+    io.W = J.W;
+    io.H = J.H;
+    io.r = r;
+    io.state = state;
+    io.cost = cost;
+    io.depth = J.depth.data;
+    io.n0 = J.normal[0].data;
+    io.n1 = J.normal[1].data;
+    io.n2 = J.normal[2].data;
+    io.cplane = J.cost.data;
+    io.pd = J.depth.pitch_elems;
+    io.pn0 = J.normal[0].pitch_elems;
+    io.pn1 = J.normal[1].pitch_elems;
+    io.pn2 = J.normal[2].pitch_elems;
+    io.pc = J.cost.pitch_elems;
 }
 
-// Tiles and grid for a launch over `cols` x `rows` pixels in (32/LPP) x 8
-// tiles; the grid is padded to a multiple of the 8 XCDs.
-dim3 tile_grid(pms::SweepArgs &A, int cols, int rows)
+void fill_geo(pms::GeoArgs &G, const JobSpec &J, int r, const Tables &T)
 {
-    const int tx = 32 / pick_variant(A.P).lpp;
-    A.tiles_x = (cols + tx - 1) / tx;
-    A.tiles_y = (rows + pms::TILE_Y - 1) / pms::TILE_Y;
-    const int tiles = A.tiles_x * A.tiles_y;
-    A.tiles_per_xcd = (tiles + 7) / 8;
-    return dim3(8 * A.tiles_per_xcd);
-}
-
-template <int DT, int LPP, int SPL, bool FULL>
-void launch_kernel(int kind, const pms::SweepArgs &A, dim3 grid, hipStream_t s)
-{
-    switch (kind) {
-    case KK_INIT: hipLaunchKernelGGL((pms::k_init<DT, LPP, SPL, FULL>), grid, dim3(pms::BLOCK), 0, s, A); break;
-    case KK_HALFSWEEP: hipLaunchKernelGGL((pms::k_halfsweep<DT, LPP, SPL, FULL>), grid, dim3(pms::BLOCK), 0, s, A); break;
-    case KK_EVAL: hipLaunchKernelGGL((pms::k_eval<DT, LPP, SPL, FULL>), grid, dim3(pms::BLOCK), 0, s, A); break;
-    default: break;
+    const int W = J.W, H = J.H;
+    G.W = W;
+    G.H = H;
+    G.r = r;
+    G.n_maps = J.n_maps;
+    G.min_views = J.p->geo_min_views > 0 ? J.p->geo_min_views : (J.n_maps < 2 ? J.n_maps : 2);
+    G.geo_px = (float)J.p->geo_px;
+    G.geo_rel = (float)J.p->geo_rel_depth;
+    const double PI = 3.14159265358979323846;
+    G.kx = (float)(W / (2.0 * PI));
+    G.cx = (float)(W / 2.0 - 0.5);
+    G.ky = (float)(-H / PI);
+    G.cy = (float)(H / 2.0 - 0.5);
+    G.tab_row = T.row;
+    G.tab_col = T.col;
+    for (int k = 0; k < J.n_maps; ++k) {
+        G.pose[k] = relative_pose(*J.ref_pose, J.map_poses[k]);
+        G.map[k] = J.maps[k].data;
+        G.map_pitch[k] = J.maps[k].pitch_elems;
     }
+    G.depth = J.depth.data;
+    G.n0 = J.normal[0].data;
+    G.n1 = J.normal[1].data;
+    G.n2 = J.normal[2].data;
+    G.cost = J.cost.data;
+    G.pd = J.depth.pitch_elems;
+    G.pn0 = J.normal[0].pitch_elems;
+    G.pn1 = J.normal[1].pitch_elems;
+    G.pn2 = J.normal[2].pitch_elems;
+    G.pc = J.cost.pitch_elems;
 }
 
-template <int DT>
-void launch_variant(int kind, const Variant &v, const pms::SweepArgs &A, dim3 grid, hipStream_t s)
+// Builds the plan of `specs`. With base == nullptr only sizes and launches
+// are final (used to size the device block); with the block's address every
+// pointer in the tables is final too.
+pms_status build_plan(pms_context *ctx, const std::vector<JobSpec> &specs, char *base, Plan &P)
 {
-    if (v.lpp == 2) launch_kernel<DT, 2, 18, true>(kind, A, grid, s);
-    else if (v.full && v.spl == 9) launch_kernel<DT, 4, 9, true>(kind, A, grid, s);
-    else if (v.full && v.spl == 16) launch_kernel<DT, 4, 16, true>(kind, A, grid, s);
-    else if (v.spl == 4) launch_kernel<DT, 4, 4, false>(kind, A, grid, s);
-    else if (v.spl == 9) launch_kernel<DT, 4, 9, false>(kind, A, grid, s);
-    else if (v.spl == 13) launch_kernel<DT, 4, 13, false>(kind, A, grid, s);
-    else launch_kernel<DT, 4, 16, false>(kind, A, grid, s);
-}
-
-pms_status launch(pms_context *ctx, int kind, int dtype, const pms::SweepArgs &A, dim3 grid,
-                  hipStream_t s)
-{
-    LaunchTimer timer(ctx, kind, s);
-    const Variant v = pick_variant(A.P);
-    switch (dtype) {
-    case PMS_F32: launch_variant<pms::DT_F32>(kind, v, A, grid, s); break;
-    case PMS_F16: launch_variant<pms::DT_F16>(kind, v, A, grid, s); break;
-    default: launch_variant<pms::DT_U8>(kind, v, A, grid, s); break;
+    P = Plan();
+    const int n = (int)specs.size();
+    std::vector<Geometry> geo(n);
+    std::vector<Tables> tabs(n);
+    for (int i = 0; i < n; ++i) {
+        pms_status st = get_tables(ctx, specs[i].W, specs[i].H, &tabs[i]);
+        if (st != PMS_OK) return st;
+        if (specs[i].mode != MODE_GEO) geo[i] = geometry(specs[i], ctx->sched);
+        else geo[i].r = (specs[i].p->patch_size - 1) / 2;
     }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(ctx, e, kKernelNames[kind]);
-    return PMS_OK;
-}
-
-// Re-lays out the neighbour images into the context's scratch.
-pms_status launch_pad(pms_context *ctx, const pms_image *nbrs, int n_nbrs, hipStream_t s)
-{
-    LaunchTimer timer(ctx, KK_IO, s);
-    const int W = nbrs[0].width, H = nbrs[0].height, Wp = ctx->pad_Wp;
-    const long long n = (long long)(H + 2) * Wp;
-    dim3 grid((unsigned)((n + pms::BLOCK - 1) / pms::BLOCK));
-    for (int j = 0; j < n_nbrs; ++j) {
-        pms::ImgRef src{nbrs[j].data, nbrs[j].pitch_bytes};
-        switch (nbrs[j].dtype) {
-        case PMS_F32:
-            hipLaunchKernelGGL(pms::k_pad<pms::DT_F32>, grid, dim3(pms::BLOCK), 0, s, src, W, H, Wp,
-                               static_cast<float *>(ctx->pad[j]));
-            break;
-        case PMS_F16:
-            hipLaunchKernelGGL(pms::k_pad<pms::DT_F16>, grid, dim3(pms::BLOCK), 0, s, src, W, H, Wp,
-                               static_cast<__half *>(ctx->pad[j]));
-            break;
-        default:
-            hipLaunchKernelGGL(pms::k_pad<pms::DT_U8>, grid, dim3(pms::BLOCK), 0, s, src, W, H, Wp,
-                               static_cast<float *>(ctx->pad[j]));
-            break;
+    // distinct neighbour images, each re-laid out once
+    std::map<std::tuple<const void *, int, int, long long, int>, int> pad_index;
+    std::vector<std::vector<int>> job_pads(n);
+    for (int i = 0; i < n; ++i) {
+        const JobSpec &J = specs[i];
+        if (J.mode == MODE_GEO) continue;
+        for (int j = 0; j < J.n_nbrs; ++j) {
+            const pms_image &im = J.nbrs[j];
+            auto key = std::make_tuple(im.data, (int)im.width, (int)im.height, (long long)im.pitch_bytes,
+                                       (int)im.dtype);
+            auto it = pad_index.find(key);
+            int idx;
+            if (it == pad_index.end()) {
+                idx = (int)P.pads.size();
+                pad_index[key] = idx;
+                pms::PadJob pj;
+                std::memset(&pj, 0, sizeof pj);
+                pj.src.ptr = im.data;
+                pj.src.pitch = im.pitch_bytes;
+                pj.W = im.width;
+                pj.H = im.height;
+                pj.Wp = 2 * im.width + 4;
+                pj.dtype = im.dtype;
+                P.pads.push_back(pj);
+            } else {
+                idx = it->second;
+            }
+            job_pads[i].push_back(idx);
         }
     }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(ctx, e, "pad");
-    return PMS_OK;
-}
 
-pms_status launch_refstats(pms_context *ctx, int dtype, const pms::SweepArgs &A, hipStream_t s)
-{
-    LaunchTimer timer(ctx, KK_REFSTATS, s);
-    const long long n = (long long)A.W * A.H;
-    dim3 grid((unsigned)((n + pms::BLOCK - 1) / pms::BLOCK));
-    switch (dtype) {
-    case PMS_F32: hipLaunchKernelGGL(pms::k_refstats<pms::DT_F32>, grid, dim3(pms::BLOCK), 0, s, A); break;
-    case PMS_F16: hipLaunchKernelGGL(pms::k_refstats<pms::DT_F16>, grid, dim3(pms::BLOCK), 0, s, A); break;
-    default: hipLaunchKernelGGL(pms::k_refstats<pms::DT_U8>, grid, dim3(pms::BLOCK), 0, s, A); break;
+    // launches, in dependency order
+    using Items = std::vector<std::tuple<int, int, int, int>>;
+    const Variant none{0, 0, false};
+    {
+        Items items;
+        for (size_t k = 0; k < P.pads.size(); ++k)
+            items.emplace_back((int)k, (int)blocks_of((long long)(P.pads[k].H + 2) * P.pads[k].Wp), 0, 0);
+        add_rec(P, KK_IO, IO_PAD, 0, none, items);
     }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(ctx, e, "refstats");
+    {
+        Items items;
+        for (int i = 0; i < n; ++i)
+            if (specs[i].mode != MODE_GEO)
+                items.emplace_back(i, (int)blocks_of((long long)specs[i].W * specs[i].H), 0, 0);
+        add_rec(P, KK_REFSTATS, 0, 0, none, items);
+    }
+    for (int i = 0; i < n; ++i)
+        if (specs[i].mode == MODE_SWEEP) {
+            Rec R{};
+            R.kind = KK_IO;
+            R.sub = IO_LOAD;
+            R.job = i;
+            R.total = 1;
+            P.recs.push_back(R);
+        }
+    // tile launches, one per group of jobs sharing a kernel instance
+    std::map<GroupKey, std::vector<int>> groups;
+    for (int i = 0; i < n; ++i)
+        if (specs[i].mode != MODE_GEO) groups[group_key(specs[i], geo[i])].push_back(i);
+    auto group_variant = [&](const std::vector<int> &js) { return geo[js[0]].v; };
+    for (auto &kv : groups) {
+        Items init, eval;
+        for (int i : kv.second) {
+            const int tiles = geo[i].tiles_x_all * geo[i].tiles_y_all;
+            if (specs[i].mode == MODE_DENSIFY) init.emplace_back(i, tiles, 0, 0);
+            if (specs[i].mode == MODE_EVAL) eval.emplace_back(i, tiles, 0, 0);
+        }
+        add_rec(P, KK_INIT, 0, std::get<0>(kv.first), group_variant(kv.second), init);
+        add_rec(P, KK_EVAL, 0, std::get<0>(kv.first), group_variant(kv.second), eval);
+    }
+    int max_steps = 0;
+    for (int i = 0; i < n; ++i)
+        if (specs[i].mode == MODE_DENSIFY) max_steps = std::max(max_steps, 2 * specs[i].p->iterations);
+        else if (specs[i].mode == MODE_SWEEP) max_steps = std::max(max_steps, 1);
+    for (int s = 0; s < max_steps; ++s)
+        for (auto &kv : groups) {
+            Items items;
+            for (int i : kv.second) {
+                const int tiles = geo[i].tiles_x_half * geo[i].tiles_y_half;
+                if (specs[i].mode == MODE_DENSIFY && s < 2 * specs[i].p->iterations)
+                    items.emplace_back(i, tiles, s / 2 + 1, s % 2);
+                if (specs[i].mode == MODE_SWEEP && s == 0)
+                    items.emplace_back(i, tiles, specs[i].iteration, specs[i].colour);
+            }
+            add_rec(P, KK_HALFSWEEP, 0, std::get<0>(kv.first), group_variant(kv.second), items);
+        }
+    {
+        Items items;
+        for (int i = 0; i < n; ++i)
+            if (specs[i].mode == MODE_DENSIFY)
+                items.emplace_back(i, (int)blocks_of((long long)specs[i].W * specs[i].H), 0, 0);
+        add_rec(P, KK_FINALIZE, 0, 0, none, items);
+    }
+    for (int i = 0; i < n; ++i)
+        if (specs[i].mode == MODE_SWEEP) {
+            Rec R{};
+            R.kind = KK_IO;
+            R.sub = IO_STORE;
+            R.job = i;
+            R.colour = specs[i].colour;
+            R.total = 1;
+            P.recs.push_back(R);
+        }
+    {
+        Items items;
+        for (int i = 0; i < n; ++i)
+            if ((specs[i].mode == MODE_DENSIFY && specs[i].n_maps > 0) || specs[i].mode == MODE_GEO)
+                items.emplace_back(i, (int)blocks_of((long long)specs[i].W * specs[i].H), 0, 0);
+        add_rec(P, KK_CONSISTENCY, 0, 0, none, items);
+    }
+
+    // layout: argument tables, then per-job state, then re-laid-out images
+    size_t off = align256((size_t)n * sizeof(pms::JobArgs));
+    P.off_pads = off;
+    off += align256(P.pads.size() * sizeof(pms::PadJob));
+    P.off_entries = off;
+    off += align256(P.entries.size() * sizeof(pms::Entry));
+    P.args_bytes = off;
+    P.jobs.resize(n);
+    for (int i = 0; i < n; ++i) {
+        const JobSpec &J = specs[i];
+        pms::JobArgs &JA = P.jobs[i];
+        std::memset(&JA, 0, sizeof JA);
+        const long long npx = (long long)J.W * J.H;
+        float4 *state = nullptr;
+        float *cost = nullptr;
+        if (J.mode == MODE_DENSIFY || J.mode == MODE_SWEEP) {
+            state = reinterpret_cast<float4 *>(base + off);
+            off += align256((size_t)npx * sizeof(float4));
+            cost = reinterpret_cast<float *>(base + off);
+            off += align256((size_t)npx * sizeof(float));
+        }
+        if (J.mode != MODE_GEO) {
+            fill_sweep_args(JA.s, J, geo[i], tabs[i]);
+            JA.s.stats = reinterpret_cast<const float2 *>(base + off);
+            off += align256((size_t)npx * sizeof(float2));
+            JA.s.state = state;
+            JA.s.cost = cost;
+        }
+        if (J.mode == MODE_EVAL) {
+            JA.s.in_depth = J.depth_in.data;
+            JA.s.in_n0 = J.normal_in[0].data;
+            JA.s.in_n1 = J.normal_in[1].data;
+            JA.s.in_n2 = J.normal_in[2].data;
+            JA.s.in_pitch = J.depth_in.pitch_elems;
+            JA.s.out_cost = J.cost.data;
+            JA.s.out_pitch = J.cost.pitch_elems;
+            for (int j = 0; j < J.n_nbrs; ++j) JA.s.view_out[j] = J.per_view ? J.per_view[j].data : nullptr;
+        }
+        if (J.mode == MODE_DENSIFY || J.mode == MODE_SWEEP) fill_io(JA.io, J, geo[i].r, state, cost);
+        if ((J.mode == MODE_DENSIFY && J.n_maps > 0) || J.mode == MODE_GEO) fill_geo(JA.g, J, geo[i].r, tabs[i]);
+    }
+    for (auto &pj : P.pads) {
+        pj.dst = base + off;
+        off += align256((size_t)(pj.H + 2) * pj.Wp * pad_elem_size(pj.dtype));
+    }
+    for (int i = 0; i < n; ++i)
+        for (size_t j = 0; j < job_pads[i].size(); ++j) P.jobs[i].s.pad[j] = P.pads[job_pads[i][j]].dst;
+    P.total_bytes = off;
     return PMS_OK;
 }
 
-pms::IoArgs io_args(pms_context *ctx, int W, int H, int r, pms_plane depth,
-                    const pms_plane normal[3], pms_plane cost)
+// Writes the argument tables of a plan into `dst` (args_bytes).
+void pack_args(const Plan &P, char *dst)
 {
-    pms::IoArgs io;
-    io.W = W;
-    io.H = H;
-    io.r = r;
-    io.state = ctx->state;
-    io.cost = ctx->cost;
-    io.depth = depth.data;
-    io.n0 = normal[0].data;
-    io.n1 = normal[1].data;
-    io.n2 = normal[2].data;
-    io.cplane = cost.data;
-    io.pd = depth.pitch_elems;
-    io.pn0 = normal[0].pitch_elems;
-    io.pn1 = normal[1].pitch_elems;
-    io.pn2 = normal[2].pitch_elems;
-    io.pc = cost.pitch_elems;
-    return io;
+    std::memset(dst, 0, P.args_bytes);
+    std::memcpy(dst, P.jobs.data(), P.jobs.size() * sizeof(pms::JobArgs));
+    std::memcpy(dst + P.off_pads, P.pads.data(), P.pads.size() * sizeof(pms::PadJob));
+    std::memcpy(dst + P.off_entries, P.entries.data(), P.entries.size() * sizeof(pms::Entry));
+}
+
+// Copies a plan's argument tables to `dev` on `s` through the staging ring.
+pms_status upload_args(pms_context *ctx, const Plan &P, void *dev, hipStream_t s)
+{
+    Staging &sl = ctx->staging[ctx->staging_next];
+    ctx->staging_next = (ctx->staging_next + 1) % kStagingSlots;
+    hipError_t e;
+    if (sl.done) {
+        e = hipEventSynchronize(sl.done);
+        if (e != hipSuccess) return hip_fail(ctx, e, "staging wait");
+    } else {
+        e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipEventCreate");
+    }
+    if (sl.cap < P.args_bytes) {
+        if (sl.host) (void)hipHostFree(sl.host);
+        sl.host = nullptr;
+        sl.cap = 0;
+        const size_t cap = std::max(P.args_bytes, (size_t)1 << 16);
+        e = hipHostMalloc(&sl.host, cap, hipHostMallocDefault);
+        if (e != hipSuccess) return fail(ctx, PMS_ERR_OUT_OF_MEMORY, "hipHostMalloc of staging failed");
+        sl.cap = cap;
+    }
+    pack_args(P, static_cast<char *>(sl.host));
+    e = hipMemcpyAsync(dev, sl.host, P.args_bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "argument upload");
+    e = hipEventRecord(sl.done, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipEventRecord");
+    return PMS_OK;
+}
+
+template <int KIND, int DT>
+void launch_tiles_dt(const Variant &v, const pms::Launch &L, dim3 grid, hipStream_t s)
+{
+    using namespace pms;
+    if (v.lpp == 2) hipLaunchKernelGGL((k_tiles<KIND, DT, 2, 18, true>), grid, dim3(BLOCK), 0, s, L);
+    else if (v.full && v.spl == 9) hipLaunchKernelGGL((k_tiles<KIND, DT, 4, 9, true>), grid, dim3(BLOCK), 0, s, L);
+    else if (v.full && v.spl == 16) hipLaunchKernelGGL((k_tiles<KIND, DT, 4, 16, true>), grid, dim3(BLOCK), 0, s, L);
+    else if (v.spl == 4) hipLaunchKernelGGL((k_tiles<KIND, DT, 4, 4, false>), grid, dim3(BLOCK), 0, s, L);
+    else if (v.spl == 9) hipLaunchKernelGGL((k_tiles<KIND, DT, 4, 9, false>), grid, dim3(BLOCK), 0, s, L);
+    else if (v.spl == 13) hipLaunchKernelGGL((k_tiles<KIND, DT, 4, 13, false>), grid, dim3(BLOCK), 0, s, L);
+    else hipLaunchKernelGGL((k_tiles<KIND, DT, 4, 16, false>), grid, dim3(BLOCK), 0, s, L);
+}
+
+template <int KIND>
+void launch_tiles(int dtype, const Variant &v, const pms::Launch &L, dim3 grid, hipStream_t s)
+{
+    if (dtype == PMS_F32) launch_tiles_dt<KIND, pms::DT_F32>(v, L, grid, s);
+    else if (dtype == PMS_F16) launch_tiles_dt<KIND, pms::DT_F16>(v, L, grid, s);
+    else launch_tiles_dt<KIND, pms::DT_U8>(v, L, grid, s);
+}
+
+// Enqueues every launch of a plan whose tables sit at `dev`.
+pms_status enqueue_plan(pms_context *ctx, const Plan &P, char *dev, hipStream_t s)
+{
+    for (const Rec &R : P.recs) {
+        LaunchTimer timer(ctx, R.kind, s);
+        if (R.kind == KK_IO && R.sub != IO_PAD) {
+            const pms::IoArgs &io = P.jobs[R.job].io;
+            dim3 grid((unsigned)blocks_of((long long)io.W * io.H));
+            if (R.sub == IO_LOAD) hipLaunchKernelGGL(pms::k_load_state, grid, dim3(pms::BLOCK), 0, s, io);
+            else hipLaunchKernelGGL(pms::k_store_colour, grid, dim3(pms::BLOCK), 0, s, io, R.colour);
+        } else {
+            pms::Launch L;
+            L.table = R.kind == KK_IO ? static_cast<const void *>(dev + P.off_pads) : static_cast<const void *>(dev);
+            L.entries = reinterpret_cast<const pms::Entry *>(dev + P.off_entries) + R.entry_off;
+            L.n_entries = R.n_entries;
+            L.per_xcd = (R.total + 7) / 8;
+            dim3 grid(8u * (unsigned)L.per_xcd);
+            switch (R.kind) {
+            case KK_IO: hipLaunchKernelGGL(pms::k_pad, grid, dim3(pms::BLOCK), 0, s, L); break;
+            case KK_REFSTATS: hipLaunchKernelGGL(pms::k_refstats, grid, dim3(pms::BLOCK), 0, s, L); break;
+            case KK_INIT: launch_tiles<pms::TK_INIT>(R.dtype, R.v, L, grid, s); break;
+            case KK_HALFSWEEP: launch_tiles<pms::TK_HALFSWEEP>(R.dtype, R.v, L, grid, s); break;
+            case KK_EVAL: launch_tiles<pms::TK_EVAL>(R.dtype, R.v, L, grid, s); break;
+            case KK_FINALIZE: hipLaunchKernelGGL(pms::k_finalize, grid, dim3(pms::BLOCK), 0, s, L); break;
+            case KK_CONSISTENCY: hipLaunchKernelGGL(pms::k_consistency, grid, dim3(pms::BLOCK), 0, s, L); break;
+            default: break;
+            }
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(ctx, e, kKernelNames[R.kind]);
+    }
+    return PMS_OK;
+}
+
+// Grows the context's device block to `need` bytes.
+pms_status ensure_work(pms_context *ctx, size_t need)
+{
+    if (need <= ctx->work_bytes) return PMS_OK;
+    if (ctx->budget && need > ctx->budget)
+        return fail(ctx, PMS_ERR_BUDGET, "device memory for this call exceeds the context budget");
+    hipError_t e;
+    if (ctx->work) {
+        // earlier work may still use the old block
+        e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipDeviceSynchronize");
+        (void)hipFree(ctx->work);
+        ctx->work = nullptr;
+        ctx->work_bytes = 0;
+    }
+    e = hipMalloc(&ctx->work, need);
+    if (e != hipSuccess) {
+        ctx->work = nullptr;
+        return fail(ctx, PMS_ERR_OUT_OF_MEMORY, "hipMalloc of the work block failed");
+    }
+    ctx->work_bytes = need;
+    return PMS_OK;
+}
+
+// Runs validated jobs through the context's own block on `s`.
+pms_status run_specs(pms_context *ctx, const std::vector<JobSpec> &specs, hipStream_t s)
+{
+    pms_status st = set_device(ctx);
+    if (st != PMS_OK) return st;
+    Plan P;
+    if ((st = build_plan(ctx, specs, nullptr, P)) != PMS_OK) return st;
+    if ((st = ensure_work(ctx, P.total_bytes)) != PMS_OK) return st;
+    char *base = static_cast<char *>(ctx->work);
+    if ((st = build_plan(ctx, specs, base, P)) != PMS_OK) return st;
+    if ((st = upload_args(ctx, P, base, s)) != PMS_OK) return st;
+    return enqueue_plan(ctx, P, base, s);
 }
 
 bool check_outputs(pms_context *ctx, int W, pms_plane depth, const pms_plane normal[3],
@@ -575,68 +947,98 @@ bool check_maps(pms_context *ctx, const pms_plane *maps, const pms_pose *map_pos
     return true;
 }
 
-pms_status launch_consistency(pms_context *ctx, int W, int H, int r, const pms_pose *ref_pose,
-                              const pms_plane *maps, const pms_pose *map_poses, int n_maps,
-                              const pms_params *p, pms_plane depth, const pms_plane normal[3],
-                              pms_plane cost, hipStream_t s)
+// Validates one densification job and fills its spec.
+bool densify_spec(pms_context *ctx, const pms_image *ref, const pms_pose *ref_pose,
+                  const pms_image *nbrs, const pms_pose *nbr_poses, int n_nbrs,
+                  const pms_plane *maps, const pms_pose *map_poses, int n_maps,
+                  const pms_params *params, pms_plane depth_out, const pms_plane normal_out[3],
+                  pms_plane cost_out, JobSpec &J, pms_status *st)
 {
-    pms::GeoArgs G;
-    std::memset(&G, 0, sizeof G);
-    G.W = W;
-    G.H = H;
-    G.r = r;
-    G.n_maps = n_maps;
-    G.min_views = p->geo_min_views > 0 ? p->geo_min_views : (n_maps < 2 ? n_maps : 2);
-    G.geo_px = (float)p->geo_px;
-    G.geo_rel = (float)p->geo_rel_depth;
-    const double PI = 3.14159265358979323846;
-    G.kx = (float)(W / (2.0 * PI));
-    G.cx = (float)(W / 2.0 - 0.5);
-    G.ky = (float)(-H / PI);
-    G.cy = (float)(H / 2.0 - 0.5);
-    G.tab_row = ctx->tab_row;
-    G.tab_col = ctx->tab_col;
-    for (int k = 0; k < n_maps; ++k) {
-        G.pose[k] = relative_pose(*ref_pose, map_poses[k]);
-        G.map[k] = maps[k].data;
-        G.map_pitch[k] = maps[k].pitch_elems;
-    }
-    G.depth = depth.data;
-    G.n0 = normal[0].data;
-    G.n1 = normal[1].data;
-    G.n2 = normal[2].data;
-    G.cost = cost.data;
-    G.pd = depth.pitch_elems;
-    G.pn0 = normal[0].pitch_elems;
-    G.pn1 = normal[1].pitch_elems;
-    G.pn2 = normal[2].pitch_elems;
-    G.pc = cost.pitch_elems;
-    LaunchTimer timer(ctx, KK_CONSISTENCY, s);
-    const long long n = (long long)W * H;
-    hipLaunchKernelGGL(pms::k_consistency, dim3((unsigned)((n + pms::BLOCK - 1) / pms::BLOCK)),
-                       dim3(pms::BLOCK), 0, s, G);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(ctx, e, "consistency");
-    return PMS_OK;
+    if (!check_ref_and_views(ctx, ref, ref_pose, nbrs, nbr_poses, n_nbrs, st)) return false;
+    const int W = ref->width, H = ref->height;
+    if (!check_params(ctx, params, W, H, n_nbrs, st)) return false;
+    if (!check_outputs(ctx, W, depth_out, normal_out, cost_out, st)) return false;
+    if (!check_maps(ctx, maps, map_poses, n_maps, W, st)) return false;
+    J = JobSpec();
+    J.mode = MODE_DENSIFY;
+    J.W = W;
+    J.H = H;
+    J.ref = ref;
+    J.ref_pose = ref_pose;
+    J.nbrs = nbrs;
+    J.nbr_poses = nbr_poses;
+    J.n_nbrs = n_nbrs;
+    J.maps = maps;
+    J.map_poses = map_poses;
+    J.n_maps = n_maps;
+    J.p = params;
+    J.depth = depth_out;
+    for (int k = 0; k < 3; ++k) J.normal[k] = normal_out[k];
+    J.cost = cost_out;
+    return true;
 }
 
-pms_status launch_io(pms_context *ctx, int which, const pms::IoArgs &io, int colour, hipStream_t s)
+bool job_spec(pms_context *ctx, const pms_job &jb, JobSpec &J, pms_status *st)
 {
-    LaunchTimer timer(ctx, which == 0 ? KK_FINALIZE : KK_IO, s);
-    const long long n = (long long)io.W * io.H;
-    dim3 grid((unsigned)((n + pms::BLOCK - 1) / pms::BLOCK));
-    if (which == 0)
-        hipLaunchKernelGGL(pms::k_finalize, grid, dim3(pms::BLOCK), 0, s, io);
-    else if (which == 1)
-        hipLaunchKernelGGL(pms::k_load_state, grid, dim3(pms::BLOCK), 0, s, io);
-    else
-        hipLaunchKernelGGL(pms::k_store_colour, grid, dim3(pms::BLOCK), 0, s, io, colour);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(ctx, e, "state io");
-    return PMS_OK;
+    return densify_spec(ctx, &jb.ref, &jb.ref_pose, jb.nbrs, jb.nbr_poses, jb.n_nbrs, jb.maps,
+                        jb.map_poses, jb.n_maps, jb.params, jb.depth_out, jb.normal_out,
+                        jb.cost_out, J, st);
+}
+
+// Output planes of one batch must not be read as another job's consistency
+// map or written by two jobs.
+bool check_batch_aliasing(pms_context *ctx, const std::vector<JobSpec> &specs, pms_status *st)
+{
+    std::vector<const float *> outs;
+    for (auto &J : specs) {
+        outs.push_back(J.depth.data);
+        for (int k = 0; k < 3; ++k) outs.push_back(J.normal[k].data);
+        outs.push_back(J.cost.data);
+    }
+    std::vector<const float *> sorted = outs;
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end()) {
+        *st = fail(ctx, PMS_ERR_INVALID_ARG, "two output planes of a batch share one buffer");
+        return false;
+    }
+    for (auto &J : specs)
+        for (int k = 0; k < J.n_maps; ++k)
+            if (std::binary_search(sorted.begin(), sorted.end(), (const float *)J.maps[k].data)) {
+                *st = fail(ctx, PMS_ERR_INVALID_ARG,
+                           "a consistency map of a batch is an output plane of the same batch");
+                return false;
+            }
+    return true;
+}
+
+bool batch_specs(pms_context *ctx, const pms_job *jobs, int n_jobs, std::vector<JobSpec> &specs,
+                 pms_status *st)
+{
+    if (n_jobs < 1 || n_jobs > PMS_MAX_BATCH || !jobs) {
+        *st = fail(ctx, PMS_ERR_INVALID_ARG, "need 1 <= n_jobs <= PMS_MAX_BATCH and a job array");
+        return false;
+    }
+    specs.resize(n_jobs);
+    for (int i = 0; i < n_jobs; ++i) {
+        if (!job_spec(ctx, jobs[i], specs[i], st)) {
+            ctx->last_error = "job " + std::to_string(i) + ": " + ctx->last_error;
+            return false;
+        }
+    }
+    return check_batch_aliasing(ctx, specs, st);
 }
 
 }  // namespace
+
+// A batch plan with its own device block, uploaded once; running it only
+// enqueues kernels (optionally as one graph launch).
+struct pms_batch {
+    pms_context *ctx = nullptr;
+    Plan plan;
+    void *block = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
 
 // ---------------------------------------------------------------------------
 // C ABI
@@ -694,13 +1096,45 @@ pms_status pms_context_destroy(pms_context *ctx)
         (void)hipSetDevice(ctx->device);
         (void)hipDeviceSynchronize();
     }
-    if (ctx->scratch) (void)hipFree(ctx->scratch);
+    if (ctx->work) (void)hipFree(ctx->work);
+    for (auto &kv : ctx->tables) (void)hipFree(kv.second.row);
+    for (auto &sl : ctx->staging) {
+        if (sl.host) (void)hipHostFree(sl.host);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+    }
+    if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
     for (auto &l : ctx->launches) {
         (void)hipEventDestroy(l.start);
         (void)hipEventDestroy(l.stop);
     }
     for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
     delete ctx;
+    return PMS_OK;
+}
+
+pms_status pms_get_schedule(const pms_context *ctx, pms_schedule *out)
+{
+    if (!ctx || !out) return PMS_ERR_INVALID_ARG;
+    out->wave_rows = 1 << ctx->sched.wy_log2;
+    out->waves_x = 1 << ctx->sched.bx_log2;
+    out->lanes_per_pixel = ctx->sched.lpp == 2 ? 2 : 4;
+    return PMS_OK;
+}
+
+pms_status pms_set_schedule(pms_context *ctx, const pms_schedule *s)
+{
+    if (!ctx || !s) return PMS_ERR_INVALID_ARG;
+    ctx->last_error.clear();
+    auto pow2 = [](int v) { return v > 0 && (v & (v - 1)) == 0; };
+    if (!pow2(s->wave_rows) || s->wave_rows > 16)
+        return fail(ctx, PMS_ERR_INVALID_ARG, "wave_rows must be 1, 2, 4, 8 or 16");
+    if (!pow2(s->waves_x) || s->waves_x > 4)
+        return fail(ctx, PMS_ERR_INVALID_ARG, "waves_x must be 1, 2 or 4");
+    if (s->lanes_per_pixel != 2 && s->lanes_per_pixel != 4)
+        return fail(ctx, PMS_ERR_INVALID_ARG, "lanes_per_pixel must be 2 or 4");
+    ctx->sched.wy_log2 = ilog2(s->wave_rows);
+    ctx->sched.bx_log2 = ilog2(s->waves_x);
+    ctx->sched.lpp = s->lanes_per_pixel == 2 ? 2 : 0;
     return PMS_OK;
 }
 
@@ -713,36 +1147,194 @@ pms_status pms_densify(pms_context *ctx, const pms_image *ref, const pms_pose *r
     if (!ctx) return PMS_ERR_INVALID_ARG;
     ctx->last_error.clear();
     pms_status st = PMS_OK;
-    if (!check_ref_and_views(ctx, ref, ref_pose, nbrs, nbr_poses, n_nbrs, &st)) return st;
-    const int W = ref->width, H = ref->height;
-    if (!check_params(ctx, params, W, H, n_nbrs, &st)) return st;
-    if (!check_outputs(ctx, W, depth_out, normal_out, cost_out, &st)) return st;
-    if (!check_maps(ctx, maps, map_poses, n_maps, W, &st)) return st;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    if ((st = ensure_scratch(ctx, W, H, n_nbrs, pad_elem_size(ref->dtype), s)) != PMS_OK) return st;
+    std::vector<JobSpec> specs(1);
+    if (!densify_spec(ctx, ref, ref_pose, nbrs, nbr_poses, n_nbrs, maps, map_poses, n_maps, params,
+                      depth_out, normal_out, cost_out, specs[0], &st))
+        return st;
+    if (!check_batch_aliasing(ctx, specs, &st)) return st;
+    return run_specs(ctx, specs, static_cast<hipStream_t>(stream));
+}
 
-    pms::SweepArgs A;
-    fill_common(A, ctx, ref, ref_pose, nbrs, nbr_poses, n_nbrs, params);
-    if ((st = launch_pad(ctx, nbrs, n_nbrs, s)) != PMS_OK) return st;
-    if ((st = launch_refstats(ctx, ref->dtype, A, s)) != PMS_OK) return st;
-    dim3 g_all = tile_grid(A, W, H);
-    if ((st = launch(ctx, KK_INIT, ref->dtype, A, g_all, s)) != PMS_OK) return st;
-    pms::SweepArgs B = A;
-    const int rows = H - 2 * A.r;
-    if (rows > 0) {
-        dim3 g_half = tile_grid(B, W / 2, rows);
-        for (int it = 1; it <= params->iterations; ++it)
-            for (int colour = 0; colour < 2; ++colour) {
-                B.iteration = it;
-                B.colour = colour;
-                if ((st = launch(ctx, KK_HALFSWEEP, ref->dtype, B, g_half, s)) != PMS_OK) return st;
-            }
+pms_status pms_densify_batch(pms_context *ctx, const pms_job *jobs, int32_t n_jobs, void *stream)
+{
+    if (!ctx) return PMS_ERR_INVALID_ARG;
+    ctx->last_error.clear();
+    pms_status st = PMS_OK;
+    std::vector<JobSpec> specs;
+    if (!batch_specs(ctx, jobs, n_jobs, specs, &st)) return st;
+    return run_specs(ctx, specs, static_cast<hipStream_t>(stream));
+}
+
+pms_status pms_batch_create(pms_context *ctx, const pms_job *jobs, int32_t n_jobs, pms_batch **out)
+{
+    if (!ctx || !out) return PMS_ERR_INVALID_ARG;
+    *out = nullptr;
+    ctx->last_error.clear();
+    pms_status st = PMS_OK;
+    std::vector<JobSpec> specs;
+    if (!batch_specs(ctx, jobs, n_jobs, specs, &st)) return st;
+    if ((st = set_device(ctx)) != PMS_OK) return st;
+    pms_batch *b = new (std::nothrow) pms_batch();
+    if (!b) return fail(ctx, PMS_ERR_OUT_OF_MEMORY, "batch allocation failed");
+    b->ctx = ctx;
+    if ((st = build_plan(ctx, specs, nullptr, b->plan)) != PMS_OK) {
+        delete b;
+        return st;
     }
-    pms::IoArgs io = io_args(ctx, W, H, A.r, depth_out, normal_out, cost_out);
-    if ((st = launch_io(ctx, 0, io, 0, s)) != PMS_OK) return st;
-    if (n_maps > 0)
-        return launch_consistency(ctx, W, H, A.r, ref_pose, maps, map_poses, n_maps, params,
-                                  depth_out, normal_out, cost_out, s);
+    if (ctx->budget && b->plan.total_bytes > ctx->budget) {
+        delete b;
+        return fail(ctx, PMS_ERR_BUDGET, "device memory for this batch exceeds the context budget");
+    }
+    hipError_t e = hipMalloc(&b->block, b->plan.total_bytes);
+    if (e != hipSuccess) {
+        delete b;
+        return fail(ctx, PMS_ERR_OUT_OF_MEMORY, "hipMalloc of the batch block failed");
+    }
+    char *base = static_cast<char *>(b->block);
+    if ((st = build_plan(ctx, specs, base, b->plan)) != PMS_OK) {
+        (void)hipFree(b->block);
+        delete b;
+        return st;
+    }
+    std::vector<char> args(b->plan.args_bytes);
+    pack_args(b->plan, args.data());
+    e = hipMemcpy(base, args.data(), args.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(b->block);
+        delete b;
+        return hip_fail(ctx, e, "batch argument upload");
+    }
+    *out = b;
+    return PMS_OK;
+}
+
+pms_status pms_batch_run(pms_batch *b, int32_t use_graph, void *stream)
+{
+    if (!b) return PMS_ERR_INVALID_ARG;
+    pms_context *ctx = b->ctx;
+    ctx->last_error.clear();
+    pms_status st = set_device(ctx);
+    if (st != PMS_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char *base = static_cast<char *>(b->block);
+    if (!use_graph) return enqueue_plan(ctx, b->plan, base, s);
+    hipError_t e;
+    if (!b->exec) {
+        if (!ctx->capture_stream) {
+            e = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking);
+            if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamCreate");
+        }
+        e = hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamBeginCapture");
+        ctx->capturing = true;
+        st = enqueue_plan(ctx, b->plan, base, ctx->capture_stream);
+        ctx->capturing = false;
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(ctx->capture_stream, &g);
+        if (st != PMS_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            b->exec = nullptr;
+            return hip_fail(ctx, e, "hipGraphInstantiate");
+        }
+        b->graph = g;
+    }
+    LaunchTimer timer(ctx, KK_GRAPH, s);
+    e = hipGraphLaunch(b->exec, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipGraphLaunch");
+    return PMS_OK;
+}
+
+pms_status pms_batch_bytes(const pms_batch *b, size_t *bytes)
+{
+    if (!b || !bytes) return PMS_ERR_INVALID_ARG;
+    *bytes = b->plan.total_bytes;
+    return PMS_OK;
+}
+
+pms_status pms_batch_destroy(pms_batch *b)
+{
+    if (!b) return PMS_ERR_INVALID_ARG;
+    if (b->ctx->device >= 0) {
+        (void)hipSetDevice(b->ctx->device);
+        (void)hipDeviceSynchronize();
+    }
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->block) (void)hipFree(b->block);
+    delete b;
+    return PMS_OK;
+}
+
+pms_status pms_autotune(pms_context *ctx, const pms_job *jobs, int32_t n_jobs, int32_t reps,
+                        int32_t try_lanes, pms_schedule *best_out, double *best_ms_out,
+                        void *stream)
+{
+    if (!ctx) return PMS_ERR_INVALID_ARG;
+    ctx->last_error.clear();
+    pms_status st = PMS_OK;
+    if (reps < 1) return fail(ctx, PMS_ERR_INVALID_ARG, "reps must be >= 1");
+    std::vector<JobSpec> specs;
+    if (!batch_specs(ctx, jobs, n_jobs, specs, &st)) return st;
+    if ((st = set_device(ctx)) != PMS_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Schedule keep = ctx->sched;
+    const bool keep_prof = ctx->profiling;
+    // earlier timings stay with the caller
+    std::vector<TimedLaunch> earlier;
+    earlier.swap(ctx->launches);
+    double best = 1e300;
+    Schedule best_s = keep;
+    const int lanes[2] = {0, 2};
+    for (int li = 0; li < (try_lanes ? 2 : 1); ++li)
+        for (int wy = 0; wy <= 4; ++wy)
+            for (int bx = 0; bx <= 2; ++bx) {
+                Schedule c;
+                c.wy_log2 = wy;
+                c.bx_log2 = bx;
+                c.lpp = try_lanes ? lanes[li] : keep.lpp;
+                ctx->sched = c;
+                ctx->profiling = false;
+                if ((st = run_specs(ctx, specs, s)) != PMS_OK) break;  // warm-up
+                ctx->profiling = true;
+                for (int k = 0; k < reps && st == PMS_OK; ++k) st = run_specs(ctx, specs, s);
+                ctx->profiling = false;
+                if (st != PMS_OK) break;
+                double ms = 0.0;
+                for (auto &l : ctx->launches) {
+                    hipError_t e = hipEventSynchronize(l.stop);
+                    if (e != hipSuccess) {
+                        st = hip_fail(ctx, e, "hipEventSynchronize");
+                        break;
+                    }
+                    float t = 0.0f;
+                    (void)hipEventElapsedTime(&t, l.start, l.stop);
+                    if (l.kind == KK_INIT || l.kind == KK_HALFSWEEP) ms += t;
+                    ctx->event_pool.push_back(l.start);
+                    ctx->event_pool.push_back(l.stop);
+                }
+                ctx->launches.clear();
+                if (st != PMS_OK) break;
+                ms /= reps;
+                if (ms < best) {
+                    best = ms;
+                    best_s = c;
+                }
+            }
+    ctx->launches.swap(earlier);
+    ctx->profiling = keep_prof;
+    if (st != PMS_OK) {
+        ctx->sched = keep;
+        return st;
+    }
+    ctx->sched = best_s;
+    if (best_out) (void)pms_get_schedule(ctx, best_out);
+    if (best_ms_out) *best_ms_out = best;
     return PMS_OK;
 }
 
@@ -770,22 +1362,22 @@ pms_status pms_eval_cost(pms_context *ctx, const pms_image *ref, const pms_pose 
                 return fail(ctx, PMS_ERR_INVALID_ARG, "per_view_out must share cost_out's pitch");
         }
     }
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    if ((st = ensure_scratch(ctx, W, H, n_nbrs, pad_elem_size(ref->dtype), s)) != PMS_OK) return st;
-    pms::SweepArgs A;
-    fill_common(A, ctx, ref, ref_pose, nbrs, nbr_poses, n_nbrs, params);
-    if ((st = launch_pad(ctx, nbrs, n_nbrs, s)) != PMS_OK) return st;
-    A.in_depth = depth_in.data;
-    A.in_n0 = normal_in[0].data;
-    A.in_n1 = normal_in[1].data;
-    A.in_n2 = normal_in[2].data;
-    A.in_pitch = pitch;
-    A.out_cost = cost_out.data;
-    A.out_pitch = cost_out.pitch_elems;
-    for (int j = 0; j < n_nbrs; ++j) A.view_out[j] = per_view_out ? per_view_out[j].data : nullptr;
-    if ((st = launch_refstats(ctx, ref->dtype, A, s)) != PMS_OK) return st;
-    dim3 g = tile_grid(A, W, H);
-    return launch(ctx, KK_EVAL, ref->dtype, A, g, s);
+    std::vector<JobSpec> specs(1);
+    JobSpec &J = specs[0];
+    J.mode = MODE_EVAL;
+    J.W = W;
+    J.H = H;
+    J.ref = ref;
+    J.ref_pose = ref_pose;
+    J.nbrs = nbrs;
+    J.nbr_poses = nbr_poses;
+    J.n_nbrs = n_nbrs;
+    J.p = params;
+    J.depth_in = depth_in;
+    for (int k = 0; k < 3; ++k) J.normal_in[k] = normal_in[k];
+    J.cost = cost_out;
+    J.per_view = per_view_out;
+    return run_specs(ctx, specs, static_cast<hipStream_t>(stream));
 }
 
 pms_status pms_halfsweep(pms_context *ctx, const pms_image *ref, const pms_pose *ref_pose,
@@ -803,22 +1395,23 @@ pms_status pms_halfsweep(pms_context *ctx, const pms_image *ref, const pms_pose 
     if (!check_outputs(ctx, W, depth_io, normal_io, cost_io, &st)) return st;
     if (iteration < 1) return fail(ctx, PMS_ERR_INVALID_ARG, "iteration must be >= 1");
     if (colour != 0 && colour != 1) return fail(ctx, PMS_ERR_INVALID_ARG, "colour must be 0 or 1");
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    if ((st = ensure_scratch(ctx, W, H, n_nbrs, pad_elem_size(ref->dtype), s)) != PMS_OK) return st;
-    pms::SweepArgs A;
-    fill_common(A, ctx, ref, ref_pose, nbrs, nbr_poses, n_nbrs, params);
-    if ((st = launch_pad(ctx, nbrs, n_nbrs, s)) != PMS_OK) return st;
-    pms::IoArgs io = io_args(ctx, W, H, A.r, depth_io, normal_io, cost_io);
-    if ((st = launch_io(ctx, 1, io, 0, s)) != PMS_OK) return st;
-    if ((st = launch_refstats(ctx, ref->dtype, A, s)) != PMS_OK) return st;
-    const int rows = H - 2 * A.r;
-    if (rows > 0) {
-        dim3 g = tile_grid(A, W / 2, rows);
-        A.iteration = iteration;
-        A.colour = colour;
-        if ((st = launch(ctx, KK_HALFSWEEP, ref->dtype, A, g, s)) != PMS_OK) return st;
-    }
-    return launch_io(ctx, 2, io, colour, s);
+    std::vector<JobSpec> specs(1);
+    JobSpec &J = specs[0];
+    J.mode = MODE_SWEEP;
+    J.W = W;
+    J.H = H;
+    J.ref = ref;
+    J.ref_pose = ref_pose;
+    J.nbrs = nbrs;
+    J.nbr_poses = nbr_poses;
+    J.n_nbrs = n_nbrs;
+    J.p = params;
+    J.depth = depth_io;
+    for (int k = 0; k < 3; ++k) J.normal[k] = normal_io[k];
+    J.cost = cost_io;
+    J.iteration = iteration;
+    J.colour = colour;
+    return run_specs(ctx, specs, static_cast<hipStream_t>(stream));
 }
 
 pms_status pms_consistency(pms_context *ctx, int32_t width, int32_t height,
@@ -838,10 +1431,20 @@ pms_status pms_consistency(pms_context *ctx, int32_t width, int32_t height,
     if (n_maps < 1) return fail(ctx, PMS_ERR_INVALID_ARG, "need at least one map");
     if (!check_maps(ctx, maps, map_poses, n_maps, width, &st)) return st;
     if (!check_outputs(ctx, width, depth_io, normal_io, cost_io, &st)) return st;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    if ((st = ensure_scratch(ctx, width, height, 0, 4, s)) != PMS_OK) return st;
-    return launch_consistency(ctx, width, height, (params->patch_size - 1) / 2, ref_pose, maps,
-                              map_poses, n_maps, params, depth_io, normal_io, cost_io, s);
+    std::vector<JobSpec> specs(1);
+    JobSpec &J = specs[0];
+    J.mode = MODE_GEO;
+    J.W = width;
+    J.H = height;
+    J.ref_pose = ref_pose;
+    J.maps = maps;
+    J.map_poses = map_poses;
+    J.n_maps = n_maps;
+    J.p = params;
+    J.depth = depth_io;
+    for (int k = 0; k < 3; ++k) J.normal[k] = normal_io[k];
+    J.cost = cost_io;
+    return run_specs(ctx, specs, static_cast<hipStream_t>(stream));
 }
 
 pms_status pms_philox_stream(pms_context *ctx, uint64_t key0, uint64_t key1, uint64_t ctr0,
@@ -852,14 +1455,13 @@ pms_status pms_philox_stream(pms_context *ctx, uint64_t key0, uint64_t key1, uin
     if (n < 0 || (n > 0 && !out)) return fail(ctx, PMS_ERR_INVALID_ARG, "bad n or null out");
     if (n == 0) return PMS_OK;
     if (n > (int64_t)1 << 31) return fail(ctx, PMS_ERR_INVALID_ARG, "n too large");
-    if (ctx->device < 0) return fail(ctx, PMS_ERR_DEVICE, "validation-only context cannot launch");
-    hipError_t e = hipSetDevice(ctx->device);
-    if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+    pms_status st = set_device(ctx);
+    if (st != PMS_OK) return st;
     hipLaunchKernelGGL(pms::k_philox, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
                        static_cast<hipStream_t>(stream), (unsigned long long)key0,
                        (unsigned long long)key1, (unsigned long long)ctr0, (long long)n,
                        reinterpret_cast<unsigned long long *>(out));
-    e = hipGetLastError();
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(ctx, e, "philox");
     return PMS_OK;
 }
@@ -916,6 +1518,496 @@ const char *pms_status_string(pms_status s)
 const char *pms_last_error(const pms_context *ctx)
 {
     return ctx ? ctx->last_error.c_str() : "";
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// serving loop: continuous batching of keyframe jobs
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// First-fit allocator over one device arena (offsets, 256-byte granules).
+class Arena {
+  public:
+    void reset(size_t bytes)
+    {
+        free_.clear();
+        size_ = bytes & ~(size_t)255;
+        if (size_) free_[0] = size_;
+        used_ = 0;
+    }
+    bool alloc(size_t bytes, size_t *off)
+    {
+        bytes = align256(bytes);
+        for (auto it = free_.begin(); it != free_.end(); ++it)
+            if (it->second >= bytes) {
+                *off = it->first;
+                const size_t rest = it->second - bytes;
+                const size_t at = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[at] = rest;
+                used_ += bytes;
+                return true;
+            }
+        return false;
+    }
+    void release(size_t off, size_t bytes)
+    {
+        bytes = align256(bytes);
+        used_ -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    size_t size() const { return size_; }
+    size_t used() const { return used_; }
+
+  private:
+    std::map<size_t, size_t> free_;
+    size_t size_ = 0, used_ = 0;
+};
+
+using ImageKey = std::tuple<const void *, int, int, long long, int>;
+
+struct CachedPad {
+    size_t off = 0, bytes = 0;
+    int refs = 0;
+    bool laid_out = false;  // its re-layout is already enqueued
+    pms::PadJob job;
+};
+
+enum ServerJobState { SJ_WAITING = 0, SJ_RUNNING = 1, SJ_DONE = 2 };
+
+// A submitted job with its own copies of everything the caller passed by
+// host pointer.
+struct ServerJob {
+    int64_t ticket = 0;
+    pms_job job{};
+    std::vector<pms_image> nbrs;
+    std::vector<pms_pose> nbr_poses, map_poses;
+    std::vector<pms_plane> maps;
+    pms_params params{};
+    JobSpec spec;
+    Geometry geo{};
+    size_t bytes = 0;      // plane state, cost and patch statistics
+    size_t pad_need = 0;   // re-laid-out images not yet cached at submission
+    size_t off = 0;
+    int slot = -1;
+    int steps_done = 0;    // half-sweeps enqueued
+    bool fresh = false;    // admitted in the tick being built
+    std::vector<ImageKey> pads;
+    int state = SJ_WAITING;
+    hipEvent_t done = nullptr;  // recorded after the job's last launch
+};
+
+}  // namespace
+
+struct pms_server {
+    pms_context *ctx = nullptr;
+    void *block = nullptr;        // argument region, then the arena
+    size_t args_bytes = 0;
+    size_t off_pads = 0, off_entries = 0;
+    int max_jobs = 0, max_pads = 0, max_entries = 0;
+    Arena arena;
+    char *arena_base = nullptr;
+    std::map<ImageKey, CachedPad> pads;
+    std::vector<pms::JobArgs> table;  // host mirror of the device job table
+    std::vector<int> slot_free;
+    std::vector<ServerJob *> waiting;  // FIFO
+    std::vector<ServerJob *> running;
+    std::map<int64_t, ServerJob *> jobs;  // every job not yet collected
+    int64_t next_ticket = 1;
+    std::vector<hipEvent_t> tick_events;  // ring: limits ticks in flight
+    int tick_next = 0;
+    std::vector<hipEvent_t> spare_events;
+    // statistics
+    int64_t ticks = 0, job_ticks = 0;
+    size_t peak_bytes = 0;
+};
+
+namespace {
+
+constexpr int kTicksInFlight = 2;
+
+// Arena bytes of a job's own buffers.
+size_t job_state_bytes(const JobSpec &J)
+{
+    const size_t npx = (size_t)J.W * J.H;
+    return align256(npx * sizeof(float4)) + align256(npx * sizeof(float)) + align256(npx * sizeof(float2));
+}
+
+ImageKey image_key(const pms_image &im)
+{
+    return ImageKey(im.data, (int)im.width, (int)im.height, (long long)im.pitch_bytes, (int)im.dtype);
+}
+
+size_t pad_bytes_of(const pms_image &im)
+{
+    return align256((size_t)(im.height + 2) * (2 * (size_t)im.width + 4) * pad_elem_size(im.dtype));
+}
+
+void server_release(pms_server *S, ServerJob *J)
+{
+    S->arena.release(J->off, J->bytes);
+    for (auto &k : J->pads) {
+        auto it = S->pads.find(k);
+        if (it != S->pads.end() && --it->second.refs == 0) {
+            S->arena.release(it->second.off, it->second.bytes);
+            S->pads.erase(it);
+        }
+    }
+    J->pads.clear();
+    S->slot_free.push_back(J->slot);
+    J->slot = -1;
+}
+
+// Tries to give the waiting job its memory and a table slot.
+bool server_admit(pms_server *S, ServerJob *J)
+{
+    if (S->slot_free.empty()) return false;
+    size_t off = 0;
+    if (!S->arena.alloc(J->bytes, &off)) return false;
+    std::vector<ImageKey> fresh_keys;
+    std::vector<ImageKey> keys;
+    for (int j = 0; j < J->job.n_nbrs; ++j) {
+        ImageKey k = image_key(J->nbrs[j]);
+        if (std::find(keys.begin(), keys.end(), k) != keys.end()) continue;
+        keys.push_back(k);
+        if (S->pads.count(k)) continue;
+        size_t poff = 0;
+        const size_t pb = pad_bytes_of(J->nbrs[j]);
+        if (!S->arena.alloc(pb, &poff)) {
+            // roll back
+            for (auto &fk : fresh_keys) {
+                S->arena.release(S->pads[fk].off, S->pads[fk].bytes);
+                S->pads.erase(fk);
+            }
+            S->arena.release(off, J->bytes);
+            return false;
+        }
+        CachedPad cp;
+        cp.off = poff;
+        cp.bytes = pb;
+        std::memset(&cp.job, 0, sizeof cp.job);
+        const pms_image &im = J->nbrs[j];
+        cp.job.src.ptr = im.data;
+        cp.job.src.pitch = im.pitch_bytes;
+        cp.job.W = im.width;
+        cp.job.H = im.height;
+        cp.job.Wp = 2 * im.width + 4;
+        cp.job.dtype = im.dtype;
+        cp.job.dst = S->arena_base + poff;
+        S->pads[k] = cp;
+        fresh_keys.push_back(k);
+    }
+    for (auto &k : keys) S->pads[k].refs += 1;
+    J->pads = keys;
+    J->off = off;
+    J->slot = S->slot_free.back();
+    S->slot_free.pop_back();
+    S->peak_bytes = std::max(S->peak_bytes, S->arena.used());
+    return true;
+}
+
+// Fills the job's table slot (host mirror).
+pms_status server_fill_slot(pms_server *S, ServerJob *J)
+{
+    Tables T;
+    pms_status st = get_tables(S->ctx, J->spec.W, J->spec.H, &T);
+    if (st != PMS_OK) return st;
+    pms::JobArgs &JA = S->table[J->slot];
+    std::memset(&JA, 0, sizeof JA);
+    char *base = S->arena_base + J->off;
+    const size_t npx = (size_t)J->spec.W * J->spec.H;
+    float4 *state = reinterpret_cast<float4 *>(base);
+    float *cost = reinterpret_cast<float *>(base + align256(npx * sizeof(float4)));
+    const float2 *stats = reinterpret_cast<const float2 *>(base + align256(npx * sizeof(float4)) +
+                                                            align256(npx * sizeof(float)));
+    fill_sweep_args(JA.s, J->spec, J->geo, T);
+    JA.s.state = state;
+    JA.s.cost = cost;
+    JA.s.stats = stats;
+    for (int j = 0; j < J->job.n_nbrs; ++j) JA.s.pad[j] = S->pads[image_key(J->nbrs[j])].job.dst;
+    fill_io(JA.io, J->spec, J->geo.r, state, cost);
+    if (J->job.n_maps > 0) fill_geo(JA.g, J->spec, J->geo.r, T);
+    return PMS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pms_status pms_server_create(pms_context *ctx, size_t arena_bytes, int32_t max_jobs, pms_server **out)
+{
+    if (!ctx || !out) return PMS_ERR_INVALID_ARG;
+    *out = nullptr;
+    ctx->last_error.clear();
+    if (max_jobs < 1 || max_jobs > PMS_MAX_BATCH)
+        return fail(ctx, PMS_ERR_INVALID_ARG, "max_jobs must be in [1, PMS_MAX_BATCH]");
+    if (arena_bytes < ((size_t)1 << 20)) return fail(ctx, PMS_ERR_INVALID_ARG, "arena below 1 MiB");
+    pms_status st = set_device(ctx);
+    if (st != PMS_OK) return st;
+    pms_server *S = new (std::nothrow) pms_server();
+    if (!S) return fail(ctx, PMS_ERR_OUT_OF_MEMORY, "server allocation failed");
+    S->ctx = ctx;
+    S->max_jobs = max_jobs;
+    S->max_pads = max_jobs * PMS_MAX_VIEWS;
+    // per tick: pads, refstats, init and half-sweep per group, finalize,
+    // consistency; each list with its sentinel
+    S->max_entries = S->max_pads + 8 * (max_jobs + 1) * 4;
+    S->off_pads = align256((size_t)max_jobs * sizeof(pms::JobArgs));
+    S->off_entries = S->off_pads + align256((size_t)S->max_pads * sizeof(pms::PadJob));
+    S->args_bytes = S->off_entries + align256((size_t)S->max_entries * sizeof(pms::Entry));
+    const size_t total = S->args_bytes + arena_bytes;
+    if (ctx->budget && total > ctx->budget) {
+        delete S;
+        return fail(ctx, PMS_ERR_BUDGET, "server arena exceeds the context budget");
+    }
+    hipError_t e = hipMalloc(&S->block, total);
+    if (e != hipSuccess) {
+        delete S;
+        return fail(ctx, PMS_ERR_OUT_OF_MEMORY, "hipMalloc of the server arena failed");
+    }
+    S->arena_base = static_cast<char *>(S->block) + S->args_bytes;
+    S->arena.reset(arena_bytes);
+    S->table.resize(max_jobs);
+    std::memset(S->table.data(), 0, S->table.size() * sizeof(pms::JobArgs));
+    for (int i = max_jobs - 1; i >= 0; --i) S->slot_free.push_back(i);
+    S->tick_events.assign(kTicksInFlight, nullptr);
+    *out = S;
+    return PMS_OK;
+}
+
+pms_status pms_server_submit(pms_server *S, const pms_job *job, int64_t *ticket)
+{
+    if (!S || !job || !ticket) return PMS_ERR_INVALID_ARG;
+    pms_context *ctx = S->ctx;
+    ctx->last_error.clear();
+    pms_status st = PMS_OK;
+    JobSpec probe;
+    if (!job_spec(ctx, *job, probe, &st)) return st;
+    std::vector<JobSpec> one{probe};
+    if (!check_batch_aliasing(ctx, one, &st)) return st;
+    ServerJob *J = new (std::nothrow) ServerJob();
+    if (!J) return fail(ctx, PMS_ERR_OUT_OF_MEMORY, "job allocation failed");
+    J->job = *job;
+    J->nbrs.assign(job->nbrs, job->nbrs + job->n_nbrs);
+    J->nbr_poses.assign(job->nbr_poses, job->nbr_poses + job->n_nbrs);
+    if (job->n_maps > 0) {
+        J->maps.assign(job->maps, job->maps + job->n_maps);
+        J->map_poses.assign(job->map_poses, job->map_poses + job->n_maps);
+    }
+    J->params = *job->params;
+    J->job.nbrs = J->nbrs.data();
+    J->job.nbr_poses = J->nbr_poses.data();
+    J->job.maps = J->maps.empty() ? nullptr : J->maps.data();
+    J->job.map_poses = J->map_poses.empty() ? nullptr : J->map_poses.data();
+    J->job.params = &J->params;
+    job_spec(ctx, J->job, J->spec, &st);
+    J->geo = geometry(J->spec, ctx->sched);
+    J->bytes = job_state_bytes(J->spec);
+    size_t need = J->bytes;
+    for (int j = 0; j < J->job.n_nbrs; ++j) need += pad_bytes_of(J->nbrs[j]);
+    if (need > S->arena.size()) {
+        delete J;
+        return fail(ctx, PMS_ERR_BUDGET, "this job alone needs more than the server arena");
+    }
+    J->ticket = S->next_ticket++;
+    S->waiting.push_back(J);
+    S->jobs[J->ticket] = J;
+    *ticket = J->ticket;
+    return PMS_OK;
+}
+
+// One tick: admit waiting jobs that fit (in arrival order), then advance
+// every admitted job by one step -- re-layout, patch statistics and the
+// random initialisation for the newly admitted ones, one half-sweep for all
+// (each at its own iteration and colour), output and consistency for those
+// that finish -- with one launch per step kind and kernel variant.
+pms_status pms_server_step(pms_server *S, void *stream, int32_t *active_out, int32_t *waiting_out)
+{
+    if (!S) return PMS_ERR_INVALID_ARG;
+    pms_context *ctx = S->ctx;
+    ctx->last_error.clear();
+    pms_status st = set_device(ctx);
+    if (st != PMS_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    // bound the ticks in flight
+    hipEvent_t &slot_ev = S->tick_events[S->tick_next];
+    if (slot_ev) {
+        e = hipEventSynchronize(slot_ev);
+        if (e != hipSuccess) return hip_fail(ctx, e, "tick wait");
+    }
+    // admission, first come first served: a job that does not fit holds
+    // back the ones behind it
+    while (!S->waiting.empty()) {
+        ServerJob *J = S->waiting.front();
+        if (!server_admit(S, J)) break;
+        S->waiting.erase(S->waiting.begin());
+        J->state = SJ_RUNNING;
+        J->fresh = true;
+        if ((st = server_fill_slot(S, J)) != PMS_OK) return st;
+        S->running.push_back(J);
+    }
+    if (active_out) *active_out = (int32_t)S->running.size();
+    if (waiting_out) *waiting_out = (int32_t)S->waiting.size();
+    if (S->running.empty()) return PMS_OK;
+
+    Plan P;
+    P.jobs = S->table;
+    P.off_pads = S->off_pads;
+    P.off_entries = S->off_entries;
+    P.args_bytes = S->args_bytes;
+    using Items = std::vector<std::tuple<int, int, int, int>>;
+    const Variant none{0, 0, false};
+    {
+        Items items;
+        for (auto &kv : S->pads)
+            if (!kv.second.laid_out) {
+                items.emplace_back((int)P.pads.size(),
+                                   (int)blocks_of((long long)(kv.second.job.H + 2) * kv.second.job.Wp), 0, 0);
+                P.pads.push_back(kv.second.job);
+                kv.second.laid_out = true;
+            }
+        add_rec(P, KK_IO, IO_PAD, 0, none, items);
+    }
+    std::map<GroupKey, std::vector<ServerJob *>> groups;
+    for (ServerJob *J : S->running) groups[group_key(J->spec, J->geo)].push_back(J);
+    {
+        Items items;
+        for (ServerJob *J : S->running)
+            if (J->fresh) items.emplace_back(J->slot, (int)blocks_of((long long)J->spec.W * J->spec.H), 0, 0);
+        add_rec(P, KK_REFSTATS, 0, 0, none, items);
+    }
+    for (auto &kv : groups) {
+        Items items;
+        for (ServerJob *J : kv.second)
+            if (J->fresh) items.emplace_back(J->slot, J->geo.tiles_x_all * J->geo.tiles_y_all, 0, 0);
+        add_rec(P, KK_INIT, 0, std::get<0>(kv.first), kv.second[0]->geo.v, items);
+    }
+    for (auto &kv : groups) {
+        Items items;
+        for (ServerJob *J : kv.second)
+            if (J->steps_done < 2 * J->params.iterations) {
+                items.emplace_back(J->slot, J->geo.tiles_x_half * J->geo.tiles_y_half,
+                                   J->steps_done / 2 + 1, J->steps_done % 2);
+                J->steps_done += 1;
+            }
+        add_rec(P, KK_HALFSWEEP, 0, std::get<0>(kv.first), kv.second[0]->geo.v, items);
+    }
+    std::vector<ServerJob *> finishing, still;
+    for (ServerJob *J : S->running) {
+        J->fresh = false;
+        if (J->steps_done >= 2 * J->params.iterations) finishing.push_back(J);
+        else still.push_back(J);
+    }
+    {
+        Items fin, geo;
+        for (ServerJob *J : finishing) {
+            fin.emplace_back(J->slot, (int)blocks_of((long long)J->spec.W * J->spec.H), 0, 0);
+            if (J->job.n_maps > 0) geo.emplace_back(J->slot, (int)blocks_of((long long)J->spec.W * J->spec.H), 0, 0);
+        }
+        add_rec(P, KK_FINALIZE, 0, 0, none, fin);
+        add_rec(P, KK_CONSISTENCY, 0, 0, none, geo);
+    }
+    if ((int)P.pads.size() > S->max_pads || (int)P.entries.size() > S->max_entries)
+        return fail(ctx, PMS_ERR_UNSUPPORTED, "tick exceeds the server's table sizes");
+    char *dev = static_cast<char *>(S->block);
+    if ((st = upload_args(ctx, P, dev, s)) != PMS_OK) return st;
+    if ((st = enqueue_plan(ctx, P, dev, s)) != PMS_OK) return st;
+    // the tick's event: completion of every job finishing in it
+    if (!slot_ev) {
+        e = hipEventCreateWithFlags(&slot_ev, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipEventCreate");
+    }
+    e = hipEventRecord(slot_ev, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipEventRecord");
+    S->tick_next = (S->tick_next + 1) % kTicksInFlight;
+    for (ServerJob *J : finishing) {
+        if (!S->spare_events.empty()) {
+            J->done = S->spare_events.back();
+            S->spare_events.pop_back();
+        } else {
+            e = hipEventCreateWithFlags(&J->done, hipEventDisableTiming);
+            if (e != hipSuccess) return hip_fail(ctx, e, "hipEventCreate");
+        }
+        e = hipEventRecord(J->done, s);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipEventRecord");
+        J->state = SJ_DONE;
+        // later ticks on this stream run after this one, so the memory can
+        // be handed out again right away
+        server_release(S, J);
+    }
+    S->ticks += 1;
+    S->job_ticks += (int64_t)S->running.size();
+    S->running.swap(still);
+    return PMS_OK;
+}
+
+pms_status pms_server_poll(pms_server *S, int64_t ticket, int32_t *state)
+{
+    if (!S || !state) return PMS_ERR_INVALID_ARG;
+    auto it = S->jobs.find(ticket);
+    if (it == S->jobs.end()) return fail(S->ctx, PMS_ERR_INVALID_ARG, "unknown or collected ticket");
+    ServerJob *J = it->second;
+    if (J->state != SJ_DONE) {
+        *state = J->state;
+        return PMS_OK;
+    }
+    hipError_t e = hipEventQuery(J->done);
+    if (e == hipErrorNotReady) {
+        *state = SJ_RUNNING;
+        return PMS_OK;
+    }
+    if (e != hipSuccess) return hip_fail(S->ctx, e, "hipEventQuery");
+    *state = SJ_DONE;
+    S->spare_events.push_back(J->done);
+    S->jobs.erase(it);
+    delete J;
+    return PMS_OK;
+}
+
+pms_status pms_server_stats(const pms_server *S, int64_t *ticks, int64_t *job_ticks,
+                            size_t *arena_used, size_t *arena_peak)
+{
+    if (!S) return PMS_ERR_INVALID_ARG;
+    if (ticks) *ticks = S->ticks;
+    if (job_ticks) *job_ticks = S->job_ticks;
+    if (arena_used) *arena_used = S->arena.used();
+    if (arena_peak) *arena_peak = S->peak_bytes;
+    return PMS_OK;
+}
+
+pms_status pms_server_destroy(pms_server *S)
+{
+    if (!S) return PMS_ERR_INVALID_ARG;
+    if (S->ctx->device >= 0) {
+        (void)hipSetDevice(S->ctx->device);
+        (void)hipDeviceSynchronize();
+    }
+    for (auto &kv : S->jobs) {
+        if (kv.second->done) (void)hipEventDestroy(kv.second->done);
+        delete kv.second;
+    }
+    for (auto e : S->tick_events)
+        if (e) (void)hipEventDestroy(e);
+    for (auto e : S->spare_events) (void)hipEventDestroy(e);
+    if (S->block) (void)hipFree(S->block);
+    delete S;
+    return PMS_OK;
 }
 
 }  // extern "C"

@@ -56,10 +56,7 @@ namespace pms {
 constexpr int MAXV = 8;       // neighbour views per launch
 constexpr int MAXOFF = 16;    // propagation offsets
 constexpr int MAXTRIAL = 16;  // refinement trials
-constexpr int TILE_Y = 8;     // tile rows per 256-thread workgroup
-template <int LPP>
-constexpr int tile_x() { return 32 / LPP; }  // tile columns
-constexpr int BLOCK = 256;
+constexpr int BLOCK = 256;    // threads per workgroup (4 waves)
 
 // Occupancy target of the PatchMatch kernels (waves per SIMD): 4 for up to
 // 9 samples per lane, where the compiler would otherwise settle for 3 waves
@@ -102,8 +99,13 @@ struct SweepArgs {
     int refine_trials;
     float sd[MAXTRIAL], sn[MAXTRIAL];
     unsigned long long seed;
-    int iteration, colour;
-    int tiles_x, tiles_y, tiles_per_xcd;
+    // tile shape: a wave covers (1 << wx_log2) x ((64 / LPP) >> wx_log2)
+    // pixels, a workgroup (1 << bx_log2) x (4 >> bx_log2) waves
+    int wx_log2, bx_log2;
+    int tile_w, tile_h;      // tile size in pixels
+    int tiles_x_all;         // tiles per tile row over all pixels
+    int tiles_x_half;        // ... over the pixels of one colour
+    int ref_dtype;
     ImgRef ref;
     ViewPoseD pose[MAXV];    // relative poses in FP64 (warped centre ray)
     ViewPoseF posef[MAXV];   // the same rounded (homography on offsets)
@@ -562,29 +564,105 @@ __device__ __forceinline__ float evaluate(const SweepArgs &A, const Patch<SPL> &
     return acc / A.k_float;
 }
 
-// Tile scheduling: logical tile t = xcd * tiles_per_xcd + slot, so that the
-// consecutive workgroups one XCD receives cover a contiguous band of tiles.
-__device__ __forceinline__ bool tile_of_block(const SweepArgs &A, int &tx, int &ty)
+// ---------------------------------------------------------------------------
+// launches over job tables
+// ---------------------------------------------------------------------------
+
+// Plane state <-> caller planes.
+struct IoArgs {
+    int W, H, r;
+    float4 *state;
+    float *cost;
+    float *depth, *n0, *n1, *n2, *cplane;
+    long long pd, pn0, pn1, pn2, pc;  // pitches in elements
+};
+
+// Geometric consistency of one keyframe against up to MAXV depth maps.
+struct GeoArgs {
+    int W, H, r, n_maps, min_views;
+    float geo_px, geo_rel;
+    float kx, cx, ky, cy;
+    const float2 *tab_row, *tab_col;
+    ViewPoseF pose[MAXV];
+    const float *map[MAXV];
+    long long map_pitch[MAXV];
+    float *depth, *n0, *n1, *n2, *cost;
+    long long pd, pn0, pn1, pn2, pc;
+};
+
+// Everything the kernels know about one keyframe job.
+struct JobArgs {
+    SweepArgs s;
+    IoArgs io;
+    GeoArgs g;
+};
+
+// One neighbour image to re-lay out.
+struct PadJob {
+    ImgRef src;
+    int W, H, Wp, dtype;
+    void *dst;
+};
+
+// A launch covers a list of entries; entry e owns the logical blocks
+// [first_e, first_{e+1}) (the list ends with a sentinel holding the total)
+// and names its job and, for a half-sweep, the job's iteration and colour.
+// Jobs at different stages of their sweep can share one launch.
+struct Entry {
+    int job, first, iteration, colour;
+};
+
+struct Launch {
+    const void *table;      // JobArgs[] or PadJob[]
+    const Entry *entries;   // n_entries + 1 entries
+    int n_entries;
+    int per_xcd;            // logical blocks per XCD; the grid is 8 * per_xcd
+};
+
+// The tables are written before a launch and only read by it: reading them
+// through the constant address space lets every (wave-uniform) access be a
+// scalar load.
+#define PMS_CONSTANT __attribute__((address_space(4)))
+
+template <typename T>
+__device__ __forceinline__ const T *const_view(const void *base, int i)
+{
+    const PMS_CONSTANT T *p = (const PMS_CONSTANT T *)base;
+    return (const T *)(p + i);
+}
+
+// Logical block of this workgroup: the 8 XCDs receive workgroups round
+// robin, and logical block t = xcd * per_xcd + slot gives each XCD a
+// contiguous run of tiles (rows of one job), whose neighbour image rows then
+// stay in that XCD's L2. Returns false past the last entry.
+__device__ __forceinline__ bool block_entry(const Launch &L, int &e, int &local)
 {
     const int bid = blockIdx.x;
-    const int t = (bid & 7) * A.tiles_per_xcd + (bid >> 3);
-    if (t >= A.tiles_x * A.tiles_y) return false;
-    ty = t / A.tiles_x;
-    tx = t - ty * A.tiles_x;
+    const int t = (bid & 7) * L.per_xcd + (bid >> 3);
+    const Entry *E = const_view<Entry>(L.entries, 0);
+    if (t >= E[L.n_entries].first) return false;
+    int lo = 0, hi = L.n_entries - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (E[mid].first <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    e = lo;
+    local = t - E[lo].first;
     return true;
 }
 
-// Position of this thread's pixel inside a (32/LPP) x 8 tile: 4 waves of
-// (16/LPP) x 4 pixels.
+// Position of this thread's pixel inside its job's tile.
 template <int LPP>
-__device__ __forceinline__ void tile_pixel(int tid, int &dx, int &dy, int &lane)
+__device__ __forceinline__ void tile_pixel(const SweepArgs &A, int tid, int &dx, int &dy, int &lane)
 {
-    constexpr int WX = 16 / LPP;
     lane = tid & (LPP - 1);
     const int wave = tid >> 6;
     const int piw = (tid & 63) / LPP;
-    dx = (wave & 1) * WX + piw % WX;
-    dy = ((wave >> 1) << 2) + piw / WX;
+    const int wx = 1 << A.wx_log2;
+    const int wy = (64 / LPP) >> A.wx_log2;
+    dx = (wave & ((1 << A.bx_log2) - 1)) * wx + (piw & (wx - 1));
+    dy = (wave >> A.bx_log2) * wy + (piw >> A.wx_log2);
 }
 
 // ---------------------------------------------------------------------------
@@ -610,35 +688,42 @@ __global__ void k_tables(int W, int H, float2 *row, float2 *col, double2 *row64,
     }
 }
 
-// Re-lays out one neighbour image: storage row py holds image row
+// Re-lays out neighbour images: storage row py holds image row
 // clamp(py - 1, 0, H - 1), storage column px holds image column
-// (px - W/2 - 2) mod W.
-template <int DT>
-__global__ __launch_bounds__(BLOCK) void k_pad(ImgRef src, int W, int H, int Wp,
-                                               typename Storage<DT>::pad_t *dst)
+// (px - W/2 - 2) mod W. 16-bit images keep their values; the others are
+// widened to FP32 (8-bit ones scaled to [0, 1]).
+template <typename TS, typename TD>
+__device__ __forceinline__ void pad_one(const PadJob &J, long long i)
 {
-    using TR = typename Storage<DT>::ref_t;
-    using PT = typename Storage<DT>::pad_t;
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (long long)(H + 2) * Wp) return;
-    const int py = (int)(i / Wp), px = (int)(i - (long long)py * Wp);
-    int sx = px - (W >> 1) - 2;
-    sx = sx < 0 ? sx + W : sx;
-    sx = sx >= W ? sx - W : sx;
-    const int sy = py == 0 ? 0 : (py > H ? H - 1 : py - 1);
-    if constexpr (DT == DT_F16)
-        dst[i] = reinterpret_cast<const __half *>(static_cast<const char *>(src.ptr) + (long long)sy * src.pitch)[sx];
+    const int py = (int)(i / J.Wp), px = (int)(i - (long long)py * J.Wp);
+    int sx = px - (J.W >> 1) - 2;
+    sx = sx < 0 ? sx + J.W : sx;
+    sx = sx >= J.W ? sx - J.W : sx;
+    const int sy = py == 0 ? 0 : (py > J.H ? J.H - 1 : py - 1);
+    if constexpr (std::is_same<TS, __half>::value)
+        static_cast<__half *>(J.dst)[i] =
+            reinterpret_cast<const __half *>(static_cast<const char *>(J.src.ptr) + (long long)sy * J.src.pitch)[sx];
     else
-        dst[i] = (PT)load_px<TR>(src, sx, sy);
+        static_cast<float *>(J.dst)[i] = load_px<TS>(J.src, sx, sy);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_pad(Launch L)
+{
+    int e, local;
+    if (!block_entry(L, e, local)) return;
+    const Entry &E = *const_view<Entry>(L.entries, e);
+    const PadJob &J = *const_view<PadJob>(L.table, E.job);
+    const long long i = (long long)local * BLOCK + threadIdx.x;
+    if (i >= (long long)(J.H + 2) * J.Wp) return;
+    if (J.dtype == DT_F16) pad_one<__half, __half>(J, i);
+    else if (J.dtype == DT_U8) pad_one<uint8_t, float>(J, i);
+    else pad_one<float, float>(J, i);
 }
 
 // Reference patch mean and variance per valid pixel (two-pass, FP32).
-template <int DT>
-__global__ __launch_bounds__(BLOCK) void k_refstats(SweepArgs A)
+template <typename TR>
+__device__ __forceinline__ void refstats_one(const SweepArgs &A, long long i)
 {
-    using TR = typename Storage<DT>::ref_t;
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (long long)A.W * A.H) return;
     const int y = (int)(i / A.W), x = (int)(i - (long long)y * A.W);
     float2 out = make_float2(0.0f, 0.0f);
     if (y >= A.r && y <= A.H - 1 - A.r) {
@@ -663,17 +748,29 @@ __global__ __launch_bounds__(BLOCK) void k_refstats(SweepArgs A)
     const_cast<float2 *>(A.stats)[i] = out;
 }
 
+__global__ __launch_bounds__(BLOCK) void k_refstats(Launch L)
+{
+    int e, local;
+    if (!block_entry(L, e, local)) return;
+    const SweepArgs &A = const_view<JobArgs>(L.table, const_view<Entry>(L.entries, e)->job)->s;
+    const long long i = (long long)local * BLOCK + threadIdx.x;
+    if (i >= (long long)A.W * A.H) return;
+    if (A.ref_dtype == DT_F16) refstats_one<__half>(A, i);
+    else if (A.ref_dtype == DT_U8) refstats_one<uint8_t>(A, i);
+    else refstats_one<float>(A, i);
+}
+
 // Random initialisation (Sec. III-B): depth uniform in inverse depth, normal
 // uniform on the sphere turned towards the camera, and its cost.
 template <int DT, int LPP, int SPL, bool FULL>
-__global__ __launch_bounds__(BLOCK) PMS_OCCUPANCY(SPL) void k_init(SweepArgs A)
+__device__ __forceinline__ void init_tile(const SweepArgs &A, int tile)
 {
     using TR = typename Storage<DT>::ref_t;
     using PT = typename Storage<DT>::pad_t;
-    int tx, ty, dx, dy, lane;
-    if (!tile_of_block(A, tx, ty)) return;
-    tile_pixel<LPP>(threadIdx.x, dx, dy, lane);
-    const int x = tx * tile_x<LPP>() + dx, y = ty * TILE_Y + dy;
+    int dx, dy, lane;
+    tile_pixel<LPP>(A, threadIdx.x, dx, dy, lane);
+    const int ty = tile / A.tiles_x_all, tx = tile - ty * A.tiles_x_all;
+    const int x = tx * A.tile_w + dx, y = ty * A.tile_h + dy;
     if (x >= A.W || y >= A.H) return;
     const long long idx = (long long)y * A.W + x;
     if (y < A.r || y > A.H - 1 - A.r) {
@@ -715,17 +812,17 @@ __global__ __launch_bounds__(BLOCK) PMS_OCCUPANCY(SPL) void k_init(SweepArgs A)
 // neighbourhood, then random refinement; strictly cheaper candidates win, the
 // first in table order on ties. Pixels of the other colour are only read.
 template <int DT, int LPP, int SPL, bool FULL>
-__global__ __launch_bounds__(BLOCK) PMS_OCCUPANCY(SPL) void k_halfsweep(SweepArgs A)
+__device__ __forceinline__ void halfsweep_tile(const SweepArgs &A, int tile, int iteration, int colour)
 {
     using TR = typename Storage<DT>::ref_t;
     using PT = typename Storage<DT>::pad_t;
-    int tx, ty, dx, dy, lane;
-    if (!tile_of_block(A, tx, ty)) return;
-    tile_pixel<LPP>(threadIdx.x, dx, dy, lane);
-    const int k = tx * tile_x<LPP>() + dx;
-    const int y = A.r + ty * TILE_Y + dy;
+    int dx, dy, lane;
+    tile_pixel<LPP>(A, threadIdx.x, dx, dy, lane);
+    const int ty = tile / A.tiles_x_half, tx = tile - ty * A.tiles_x_half;
+    const int k = tx * A.tile_w + dx;
+    const int y = A.r + ty * A.tile_h + dy;
     if (k >= (A.W >> 1) || y > A.H - 1 - A.r) return;
-    const int x = 2 * k + ((y + A.colour) & 1);
+    const int x = 2 * k + ((y + colour) & 1);
     const long long idx = (long long)y * A.W + x;
 
     Patch<SPL> pt;
@@ -760,7 +857,7 @@ __global__ __launch_bounds__(BLOCK) PMS_OCCUPANCY(SPL) void k_halfsweep(SweepArg
 
     for (int t = 0; t < A.refine_trials; ++t) {
         float u[4];
-        uniforms(A.seed, (unsigned long long)idx, (unsigned long long)A.iteration,
+        uniforms(A.seed, (unsigned long long)idx, (unsigned long long)iteration,
                  (unsigned long long)(16 + t), u);
         float dd = bd * expf((2.0f * u[0] - 1.0f) * A.sd[t]);
         dd = fminf(fmaxf(dd, A.dmin), A.dmax);
@@ -790,14 +887,14 @@ __global__ __launch_bounds__(BLOCK) PMS_OCCUPANCY(SPL) void k_halfsweep(SweepArg
 
 // Cost of caller-given hypotheses at every pixel (the matching cost alone).
 template <int DT, int LPP, int SPL, bool FULL>
-__global__ __launch_bounds__(BLOCK) PMS_OCCUPANCY(SPL) void k_eval(SweepArgs A)
+__device__ __forceinline__ void eval_tile(const SweepArgs &A, int tile)
 {
     using TR = typename Storage<DT>::ref_t;
     using PT = typename Storage<DT>::pad_t;
-    int tx, ty, dx, dy, lane;
-    if (!tile_of_block(A, tx, ty)) return;
-    tile_pixel<LPP>(threadIdx.x, dx, dy, lane);
-    const int x = tx * tile_x<LPP>() + dx, y = ty * TILE_Y + dy;
+    int dx, dy, lane;
+    tile_pixel<LPP>(A, threadIdx.x, dx, dy, lane);
+    const int ty = tile / A.tiles_x_all, tx = tile - ty * A.tiles_x_all;
+    const int x = tx * A.tile_w + dx, y = ty * A.tile_h + dy;
     if (x >= A.W || y >= A.H) return;
     const long long pin = (long long)y * A.in_pitch + x;
     const long long pout = (long long)y * A.out_pitch + x;
@@ -820,19 +917,25 @@ __global__ __launch_bounds__(BLOCK) PMS_OCCUPANCY(SPL) void k_eval(SweepArgs A)
     if (lane == 0) A.out_cost[pout] = c;
 }
 
-// Plane state <-> caller planes.
-struct IoArgs {
-    int W, H, r;
-    float4 *state;
-    float *cost;
-    float *depth, *n0, *n1, *n2, *cplane;
-    long long pd, pn0, pn1, pn2, pc;  // pitches in elements
-};
+enum TileKind { TK_INIT = 0, TK_HALFSWEEP = 1, TK_EVAL = 2 };
 
-__global__ __launch_bounds__(BLOCK) void k_finalize(IoArgs A)
+// The PatchMatch kernels: every workgroup serves one tile of one job.
+template <int KIND, int DT, int LPP, int SPL, bool FULL>
+__global__ __launch_bounds__(BLOCK) PMS_OCCUPANCY(SPL) void k_tiles(Launch L)
 {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (long long)A.W * A.H) return;
+    int e, local;
+    if (!block_entry(L, e, local)) return;
+    const Entry &E = *const_view<Entry>(L.entries, e);
+    const SweepArgs &A = const_view<JobArgs>(L.table, E.job)->s;
+    if (KIND == TK_INIT) init_tile<DT, LPP, SPL, FULL>(A, local);
+    else if (KIND == TK_HALFSWEEP) halfsweep_tile<DT, LPP, SPL, FULL>(A, local, E.iteration, E.colour);
+    else eval_tile<DT, LPP, SPL, FULL>(A, local);
+}
+
+// Caller planes from the plane state (invalid pixels: depth and normal 0,
+// cost 2).
+__device__ __forceinline__ void finalize_one(const IoArgs &A, long long i)
+{
     const int y = (int)(i / A.W), x = (int)(i - (long long)y * A.W);
     const float4 s = A.state[i];
     const bool ok = y >= A.r && y <= A.H - 1 - A.r && s.w > 0.0f;
@@ -843,6 +946,17 @@ __global__ __launch_bounds__(BLOCK) void k_finalize(IoArgs A)
     A.cplane[(long long)y * A.pc + x] = ok ? A.cost[i] : 2.0f;
 }
 
+__global__ __launch_bounds__(BLOCK) void k_finalize(Launch L)
+{
+    int e, local;
+    if (!block_entry(L, e, local)) return;
+    const IoArgs &A = const_view<JobArgs>(L.table, const_view<Entry>(L.entries, e)->job)->io;
+    const long long i = (long long)local * BLOCK + threadIdx.x;
+    if (i >= (long long)A.W * A.H) return;
+    finalize_one(A, i);
+}
+
+// Plane state from caller planes (test hook).
 __global__ __launch_bounds__(BLOCK) void k_load_state(IoArgs A)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -872,18 +986,6 @@ __global__ __launch_bounds__(BLOCK) void k_store_colour(IoArgs A, int colour)
 // geometric consistency
 // ---------------------------------------------------------------------------
 
-struct GeoArgs {
-    int W, H, r, n_maps, min_views;
-    float geo_px, geo_rel;
-    float kx, cx, ky, cy;
-    const float2 *tab_row, *tab_col;
-    ViewPoseF pose[MAXV];
-    const float *map[MAXV];
-    long long map_pitch[MAXV];
-    float *depth, *n0, *n1, *n2, *cost;
-    long long pd, pn0, pn1, pn2, pc;
-};
-
 __device__ __forceinline__ void project(const GeoArgs &A, float y0, float y1, float y2, float &u,
                                         float &v)
 {
@@ -898,10 +1000,8 @@ __device__ __forceinline__ void project(const GeoArgs &A, float y0, float y1, fl
 // require both the reprojection error (pixels, longitude folded across the
 // seam) and the relative range error to be within bounds; keep the pixel if
 // at least min_views maps agree.
-__global__ __launch_bounds__(BLOCK) void k_consistency(GeoArgs A)
+__device__ __forceinline__ void consistency_one(const GeoArgs &A, long long i)
 {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (long long)A.W * A.H) return;
     const int y = (int)(i / A.W), x = (int)(i - (long long)y * A.W);
     const long long id = (long long)y * A.pd + x;
     const float d = A.depth[id];
@@ -948,6 +1048,16 @@ __global__ __launch_bounds__(BLOCK) void k_consistency(GeoArgs A)
         A.n2[(long long)y * A.pn2 + x] = 0.0f;
         A.cost[(long long)y * A.pc + x] = 2.0f;
     }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_consistency(Launch L)
+{
+    int e, local;
+    if (!block_entry(L, e, local)) return;
+    const GeoArgs &A = const_view<JobArgs>(L.table, const_view<Entry>(L.entries, e)->job)->g;
+    const long long i = (long long)local * BLOCK + threadIdx.x;
+    if (i >= (long long)A.W * A.H) return;
+    consistency_one(A, i);
 }
 
 // Test hook: raw Philox blocks.

@@ -185,6 +185,8 @@ BASE_PARAMS = dict(
 
 def params_for(name: str, **over) -> dict:
     p = dict(BASE_PARAMS)
+    if name.startswith("hall7"):
+        name = "hall"
     if name.startswith("box_room"):
         p.update(patch_size=7, patch_stride=1, iterations=4, depth_min=0.3, depth_max=10.0)
     elif name.startswith("hall"):
@@ -246,9 +248,9 @@ def _trajectory_keyframes(rng, n_kf, spacing, xlim, zlim, height, dh):
     return np.array(centres), np.array(yaws)
 
 
-def _hall(rng, W, ss):
+def _hall_n(rng, n_kf):
     xlim, ylo, zlim = 12.0, -8.0, 8.0
-    centres, yaws = _trajectory_keyframes(rng, 5, (0.25, 0.5), 8.0, 4.5, 1.5, 0.5)
+    centres, yaws = _trajectory_keyframes(rng, n_kf, (0.25, 0.5), 8.0, 4.5, 1.5, 0.5)
     prims = [_prim(PRIM_ROOM, [-xlim, ylo, -zlim], [xlim, 0.0, zlim])]
 
     def clear(p, radius):
@@ -281,7 +283,20 @@ def _hall(rng, W, ss):
     scene = _scene(prims, n_octaves=4, base_freq=2.5, tex_seed=int(rng.integers(1 << 62)))
     poses = [camera_pose(c, y, rng.uniform(-0.05, 0.05), rng.uniform(-0.05, 0.05))
              for c, y in zip(centres, yaws)]
-    return scene, poses, 2, [0, 1, 3, 4], [0, 1, 3, 4]
+    mid = n_kf // 2
+    others = [k for k in range(n_kf) if k != mid]
+    return scene, poses, mid, others, others
+
+
+def _hall(rng, W, ss):
+    """Five keyframes; the middle one is the reference."""
+    return _hall_n(rng, 5)
+
+
+def _hall7(rng, W, ss):
+    """The same hall generator with seven keyframes (up to six
+    neighbours), for the mixed batch and serving workloads."""
+    return _hall_n(rng, 7)
 
 
 def _courtyard(rng, W, ss):
@@ -310,6 +325,7 @@ def _courtyard(rng, W, ss):
 
 _BUILDERS = {"box_room": (_box_room, 256, "f32"),
              "hall": (_hall, 1920, "f32"),
+             "hall7": (_hall7, 1920, "f32"),
              "courtyard": (_courtyard, 3840, "u8")}
 
 WORKLOADS = {"box_room_256": ("box_room", 256),
@@ -355,3 +371,63 @@ def scaled(family_or_name: str, W: int, seed: int = 0, ss: int | None = None,
 def workload(name: str, seed: int = 0, **param_over) -> Workload:
     family, W = WORKLOADS[name]
     return scaled(family, W, seed=seed, **param_over)
+
+
+# ----------------------------------------------------------------------------
+# mixed batches and request streams (uneven keyframe jobs)
+# ----------------------------------------------------------------------------
+
+MIXED_WIDTHS = (960, 1920, 2880)
+
+
+def mixed_pool(seed: int = 0, widths=MIXED_WIDTHS, dtype: str = "f16") -> dict:
+    """One seven-keyframe hall window per image width, rendered with the
+    hall generator and parameters; `dtype` "f16" stores the intensities in
+    float16, "f32" in float32."""
+    pool = {}
+    for k, W in enumerate(widths):
+        w = scaled("hall7", W, seed=seed + 101 * k)
+        if dtype == "f16":
+            w.images = [a.astype(np.float16) for a in w.images]
+            w.dtype = "f16"
+        pool[W] = w
+    return pool
+
+
+@dataclasses.dataclass
+class MixedJob:
+    W: int            # image width of the job's window
+    ref: int          # reference keyframe index in the window
+    nbrs: list        # neighbour keyframe indices (nearest along the path)
+    seed: int         # PatchMatch seed of the job
+
+
+def _mixed_job(rng, W, n_range, n_kf):
+    N = int(rng.integers(n_range[0], n_range[1] + 1))
+    ref = int(rng.integers(0, n_kf))
+    others = sorted((k for k in range(n_kf) if k != ref), key=lambda k: (abs(k - ref), k))[:N]
+    return MixedJob(W, ref, sorted(others), int(rng.integers(1 << 31)))
+
+
+def mixed_jobs(n_by_width: dict, seed: int = 0, n_range=(3, 6), n_kf: int = 7) -> list:
+    """`n_by_width[W]` jobs of width W, each with N ~ U{n_range} neighbours
+    around a random reference of the window, in a seeded shuffled order."""
+    rng = np.random.default_rng(seed)
+    jobs = [_mixed_job(rng, W, n_range, n_kf) for W, n in n_by_width.items() for _ in range(n)]
+    return [jobs[i] for i in rng.permutation(len(jobs))]
+
+
+def poisson_requests(n_streams: int, rate_hz: float, horizon_s: float, seed: int = 0,
+                     widths=MIXED_WIDTHS, n_range=(3, 6), n_kf: int = 7) -> list:
+    """Arrivals of n_streams independent Poisson processes of rate rate_hz
+    over [0, horizon_s); each request draws its width uniformly from
+    `widths` and N ~ U{n_range}. Returns sorted (time, stream, MixedJob)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for s in range(n_streams):
+        t = rng.exponential(1.0 / rate_hz)
+        while t < horizon_s:
+            W = int(widths[int(rng.integers(0, len(widths)))])
+            out.append((float(t), s, _mixed_job(rng, W, n_range, n_kf)))
+            t += rng.exponential(1.0 / rate_hz)
+    return sorted(out, key=lambda r: r[0])

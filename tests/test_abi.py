@@ -163,3 +163,88 @@ def test_status_strings(B):
     for s in range(6):
         assert L.pms_status_string(s)
     assert L.pms_status_string(99) == b"unknown status"
+
+
+def test_struct_sizes_of_batch_types(B):
+    # pms_job: image 32 + pose 96 + 2 pointers + int (padded to 8) + 2 pointers
+    # + int (padded) + params pointer + 5 planes
+    assert C.sizeof(B.Job) == 32 + 96 + 16 + 8 + 16 + 8 + 8 + 5 * 16
+    assert C.sizeof(B.Schedule) == 12
+
+
+def _job(B, c, depth_at=0x9000):
+    """A pms_job over the fake buffers of a _Call; outputs at `depth_at`."""
+    j = B.Job()
+    j.ref = c.ref
+    j.ref_pose = c.pose
+    j.nbrs = C.cast(c.nbrs, C.POINTER(B.Image))
+    j.nbr_poses = C.cast(c.nposes, C.POINTER(B.Pose))
+    j.n_nbrs = c.n
+    j.n_maps = 0
+    j.params = C.pointer(c.params)
+    W = c.ref.width
+    j.depth_out = B.Plane(0x100000 + depth_at, W)
+    for k in range(3):
+        j.normal_out[k] = B.Plane(0x100000 + depth_at + 0x100 * (k + 1), W)
+    j.cost_out = B.Plane(0x100000 + depth_at + 0x400, W)
+    return j
+
+
+def test_batch_entry_points_validate(B, vctx):
+    L = B.lib()
+    calls = [_Call(B, W=64), _Call(B, W=128, n=3, dtype=1)]
+    jobs = (B.Job * 2)(_job(B, calls[0], 0x1000), _job(B, calls[1], 0x2000))
+    assert L.pms_densify_batch(vctx, jobs, 2, None) == DEVICE
+    assert L.pms_densify_batch(vctx, jobs, 0, None) == INVALID
+    assert L.pms_densify_batch(vctx, None, 2, None) == INVALID
+    h = C.c_void_p()
+    assert L.pms_batch_create(vctx, jobs, 2, C.byref(h)) == DEVICE
+    assert not h.value
+    sc = B.Schedule()
+    best = C.c_double()
+    assert L.pms_autotune(vctx, jobs, 2, 1, 0, C.byref(sc), C.byref(best), None) == DEVICE
+    assert L.pms_autotune(vctx, jobs, 2, 0, 0, C.byref(sc), C.byref(best), None) == INVALID
+    # a malformed job names itself
+    calls[1].params.patch_size = 8
+    assert L.pms_densify_batch(vctx, jobs, 2, None) == INVALID
+    assert L.pms_last_error(vctx).startswith(b"job 1:")
+    calls[1].params.patch_size = 7
+    # two jobs writing one plane
+    jobs[1].cost_out = jobs[0].cost_out
+    assert L.pms_densify_batch(vctx, jobs, 2, None) == INVALID
+    jobs[1].cost_out = B.Plane(0x100000 + 0x2400, 128)
+    # a consistency map that another job writes
+    maps = (B.Plane * 1)(jobs[0].depth_out)
+    mposes = (B.Pose * 1)(calls[1].nposes[0])
+    maps[0].pitch_elems = 128
+    jobs[1].maps = C.cast(maps, C.POINTER(B.Plane))
+    jobs[1].map_poses = C.cast(mposes, C.POINTER(B.Pose))
+    jobs[1].n_maps = 1
+    assert L.pms_densify_batch(vctx, jobs, 2, None) == INVALID
+    jobs[1].n_maps = 0
+    assert L.pms_densify_batch(vctx, jobs, 2, None) == DEVICE
+
+
+def test_schedule_round_trip_and_rejection(B, vctx):
+    L = B.lib()
+    sc = B.Schedule()
+    assert L.pms_get_schedule(vctx, C.byref(sc)) == OK
+    assert (sc.wave_rows, sc.waves_x, sc.lanes_per_pixel) == (4, 2, 4)
+    for bad in [(3, 2, 4), (32, 2, 4), (4, 8, 4), (4, 3, 4), (4, 2, 1), (0, 2, 4)]:
+        assert L.pms_set_schedule(vctx, C.byref(B.Schedule(*bad))) == INVALID
+    assert L.pms_set_schedule(vctx, C.byref(B.Schedule(16, 1, 2))) == OK
+    assert L.pms_get_schedule(vctx, C.byref(sc)) == OK
+    assert (sc.wave_rows, sc.waves_x, sc.lanes_per_pixel) == (16, 1, 2)
+
+
+def test_server_entry_points_validate(B, vctx):
+    L = B.lib()
+    h = C.c_void_p()
+    assert L.pms_server_create(vctx, 1 << 26, 0, C.byref(h)) == INVALID
+    assert L.pms_server_create(vctx, 1 << 10, 4, C.byref(h)) == INVALID
+    assert L.pms_server_create(vctx, 1 << 26, 4, C.byref(h)) == DEVICE
+    assert not h.value
+    assert L.pms_server_submit(None, None, None) == INVALID
+    assert L.pms_server_step(None, None, None, None) == INVALID
+    st = C.c_int32()
+    assert L.pms_server_poll(None, 1, C.byref(st)) == INVALID
