@@ -109,6 +109,8 @@ def lib() -> C.CDLL:
                                             _D, _D, _D, C.c_int, C.c_int, C.c_int, C.c_int,
                                             _D, _D, _D, C.c_int]
         L.pmsref_pixel_valid.argtypes = [C.c_int, C.c_int, C.POINTER(Params), C.c_int, C.c_int]
+        L.pmsref_warp_planes.argtypes = [C.c_int, C.c_int, _D, _D, C.POINTER(Pose), C.POINTER(Pose),
+                                         C.POINTER(Params), _D, _D]
         _lib = L
     return _lib
 
@@ -388,3 +390,19 @@ def densify(ref, nbrs, ref_pose, nbr_poses, params: dict, init_depth=None, init_
     if rc:
         raise ValueError(f"pmsref_densify failed: {rc}")
     return depth, normal, cost
+
+
+def warp_planes(src_depth, src_normal, src_pose, dst_pose, params: dict):
+    """Plane map of the keyframe at src_pose carried into the keyframe at
+    dst_pose (Sec. III-B). Returns (depth (H,W), normal (3,H,W)); depth 0
+    where no plane arrives."""
+    sd = _f64(src_depth)
+    sn = _f64(src_normal)
+    H, W = sd.shape
+    dd = np.zeros((H, W))
+    dn = np.zeros((3, H, W))
+    rc = lib().pmsref_warp_planes(W, H, _dptr(sd), _dptr(sn), _poses([src_pose]), _poses([dst_pose]),
+                                  C.byref(make_params(params)), _dptr(dd), _dptr(dn))
+    if rc:
+        raise ValueError(f"pmsref_warp_planes failed: {rc}")
+    return dd, dn

@@ -919,3 +919,79 @@ int pmsref_densify(int W, int H, const double *ref, int n_views, const double *c
                                   NULL, NULL, NULL, n_threads);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* plane-map warping (Sec. III-B: the optimised plane map of the preceding  */
+/* keyframe initialises the current one; after Shen 2013). The paper's      */
+/* listing of the step is a figure that is not in the text; the reading:    */
+/* every valid source pixel carries its plane point X = d b into the        */
+/* destination camera (Y = R X + t, relative pose composed in FP64), where  */
+/* it claims the nearest pixel; of the claims on one pixel the nearest point */
+/* wins (range rounded to float, ties to the lower source index, so that    */
+/* the choice is the one a float z-buffer makes); the winner's plane,       */
+/* normal R n through Y, is re-intersected with the claimed pixel's own     */
+/* ray. Parity: pinned by tests (identity, exact yaw shift, analytic        */
+/* planes, occlusion by a nearer plane, back-facing planes).                */
+/* ------------------------------------------------------------------------ */
+
+int pmsref_warp_planes(int W, int H, const double *src_depth, const double *src_normal,
+                       const pmsref_pose *src_pose, const pmsref_pose *dst_pose,
+                       const pmsref_params *p, double *dst_depth, double *dst_normal)
+{
+    int rc = pmsref_check_params(p, W, H, 0);
+    if (rc) return rc;
+    if (!src_depth || !src_normal || !src_pose || !dst_pose || !dst_depth || !dst_normal) return -1;
+    long HW = (long)W * H;
+    double R[9], t[3];
+    pmsref_relative_pose(src_pose, dst_pose, R, t);
+    uint64_t *best = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)HW);
+    if (!best) return -20;
+    for (long i = 0; i < HW; ++i) best[i] = UINT64_MAX;
+    /* claims */
+    for (long i = 0; i < HW; ++i) {
+        int x = (int)(i % W), y = (int)(i / W);
+        double d = src_depth[i];
+        if (!pmsref_pixel_valid(W, H, p, x, y) || !(d > 0.0)) continue;
+        double b[3], X[3], Y[3];
+        pmsref_unproject(W, H, x, y, b);
+        for (int k = 0; k < 3; ++k) X[k] = d * b[k];
+        for (int k = 0; k < 3; ++k) Y[k] = R[3 * k] * X[0] + R[3 * k + 1] * X[1] + R[3 * k + 2] * X[2] + t[k];
+        double range = sqrt(dot3(Y, Y));
+        if (!(range > 0.0)) continue;
+        double u, v;
+        pmsref_project(W, H, Y, &u, &v);
+        int xi = wrap_index(floor(u + 0.5), W);
+        int yi = clamp_index(floor(v + 0.5), H);
+        if (!pmsref_pixel_valid(W, H, p, xi, yi)) continue;
+        float rf = (float)range;
+        uint32_t bits;
+        memcpy(&bits, &rf, sizeof bits);
+        uint64_t key = ((uint64_t)bits << 32) | (uint64_t)(uint32_t)i;
+        long j = (long)yi * W + xi;
+        if (key < best[j]) best[j] = key;
+    }
+    /* resolution: the winning plane at each claimed pixel */
+    for (long j = 0; j < HW; ++j) {
+        dst_depth[j] = 0.0;
+        dst_normal[j] = dst_normal[HW + j] = dst_normal[2 * HW + j] = 0.0;
+        if (best[j] == UINT64_MAX) continue;
+        long i = (long)(best[j] & 0xffffffffu);
+        int x = (int)(i % W), y = (int)(i / W);
+        int xd = (int)(j % W), yd = (int)(j / W);
+        double b[3], X[3], Y[3], n[3], nd[3], bd[3];
+        pmsref_unproject(W, H, x, y, b);
+        for (int k = 0; k < 3; ++k) X[k] = src_depth[i] * b[k];
+        for (int k = 0; k < 3; ++k) Y[k] = R[3 * k] * X[0] + R[3 * k + 1] * X[1] + R[3 * k + 2] * X[2] + t[k];
+        for (int k = 0; k < 3; ++k) n[k] = src_normal[(long)k * HW + i];
+        for (int k = 0; k < 3; ++k) nd[k] = R[3 * k] * n[0] + R[3 * k + 1] * n[1] + R[3 * k + 2] * n[2];
+        pmsref_unproject(W, H, xd, yd, bd);
+        double den = dot3(nd, bd);
+        if (!(den < 0.0)) continue;
+        double dd = dot3(nd, Y) / den;
+        if (!(dd >= p->depth_min && dd <= p->depth_max)) continue;
+        dst_depth[j] = dd;
+        for (int k = 0; k < 3; ++k) dst_normal[(long)k * HW + j] = nd[k];
+    }
+    free(best);
+    return 0;
+}

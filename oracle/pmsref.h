@@ -167,6 +167,19 @@ int pmsref_densify(int W, int H, const double *ref, int n_views,
                    double *normal_out, double *cost_out, int n_threads,
                    uint64_t order_seed);
 
+/* --- plane-map warping (Sec. III-B) ------------------------------------------
+   Carries the plane map (src_depth H*W, 0 = none; src_normal 3*H*W planar)
+   of the keyframe at src_pose into the keyframe at dst_pose: each valid
+   source pixel claims the destination pixel nearest to the projection of its
+   plane point, the nearest claim wins (float range, then lower source
+   index), and its plane (rotated normal) is re-intersected with the
+   destination pixel's ray. Outputs dst_depth (0 = no plane) and dst_normal
+   (0 = none); only depths in [depth_min, depth_max] with the normal facing
+   the destination camera are kept. Returns 0 or a negative code. */
+int pmsref_warp_planes(int W, int H, const double *src_depth, const double *src_normal,
+                       const pmsref_pose *src_pose, const pmsref_pose *dst_pose,
+                       const pmsref_params *p, double *dst_depth, double *dst_normal);
+
 /* Pixels per row-band for which pmsref_update_pixel is defined (valid rows). */
 int pmsref_pixel_valid(int W, int H, const pmsref_params *p, int x, int y);
 
