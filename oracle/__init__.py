@@ -59,6 +59,8 @@ class Params(C.Structure):
         ("geo_rel_depth", C.c_double),
         ("geo_min_views", C.c_int32),
         ("seed", C.c_uint64),
+        ("median_radius", C.c_int32),
+        ("median_rel", C.c_double),
     ]
 
 
@@ -109,6 +111,7 @@ def lib() -> C.CDLL:
                                             _D, _D, _D, C.c_int, C.c_int, C.c_int, C.c_int,
                                             _D, _D, _D, C.c_int]
         L.pmsref_pixel_valid.argtypes = [C.c_int, C.c_int, C.POINTER(Params), C.c_int, C.c_int]
+        L.pmsref_median_filter.argtypes = [C.c_int, C.c_int, _D, _D, _D, C.POINTER(Params)]
         L.pmsref_warp_planes.argtypes = [C.c_int, C.c_int, _D, _D, C.POINTER(Pose), C.POINTER(Pose),
                                          C.POINTER(Params), _D, _D]
         _lib = L
@@ -406,3 +409,16 @@ def warp_planes(src_depth, src_normal, src_pose, dst_pose, params: dict):
     if rc:
         raise ValueError(f"pmsref_warp_planes failed: {rc}")
     return dd, dn
+
+
+def median_filter(depth, normal, cost, params: dict):
+    """Median post-filter (Sec. III-C item 2) of copies of the maps."""
+    depth = _f64(depth).copy()
+    normal = _f64(normal).copy()
+    cost = _f64(cost).copy()
+    H, W = depth.shape
+    rc = lib().pmsref_median_filter(W, H, _dptr(depth), _dptr(normal), _dptr(cost),
+                                    C.byref(make_params(params)))
+    if rc:
+        raise ValueError(f"pmsref_median_filter failed: {rc}")
+    return depth, normal, cost

@@ -78,6 +78,8 @@ void pmsref_default_params(pmsref_params *p)
     p->geo_rel_depth = 0.01;
     p->geo_min_views = 0;
     p->seed = 0;
+    p->median_radius = 0;
+    p->median_rel = 0.05;
 }
 
 static int patch_radius(const pmsref_params *p) { return (p->patch_size - 1) / 2; }
@@ -119,6 +121,8 @@ int pmsref_check_params(const pmsref_params *p, int W, int H, int n_views)
         if (oy <= -H || oy >= H || ox <= -W || ox >= W) return -13;
     }
     if (!(p->geo_px >= 0.0) || !(p->geo_rel_depth >= 0.0) || p->geo_min_views < 0) return -14;
+    if (p->median_radius < 0 || p->median_radius > 8 || !(p->median_rel >= 0.0) || !isfinite(p->median_rel))
+        return -15;
     return 0;
 }
 
@@ -914,6 +918,8 @@ int pmsref_densify(int W, int H, const double *ref, int n_views, const double *c
     free(nn);
     free(nc);
 
+    rc = pmsref_median_filter(W, H, depth, normal, cost, p);
+    if (rc) return rc;
     if (n_maps > 0)
         return pmsref_consistency(W, H, depth, normal, cost, ref_pose, n_maps, maps, map_poses, p,
                                   NULL, NULL, NULL, n_threads);
@@ -993,5 +999,65 @@ int pmsref_warp_planes(int W, int H, const double *src_depth, const double *src_
         for (int k = 0; k < 3; ++k) dst_normal[(long)k * HW + j] = nd[k];
     }
     free(best);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* median post-filter (Sec. III-C, item 2: a median-filtered copy of the    */
+/* depth image is compared with the original and depths deviating beyond a */
+/* threshold are removed). Window, median of an even count and the relative */
+/* threshold are readings. Parity: pinned by tests (flat maps, an isolated  */
+/* outlier, brute force against numpy on random maps, the seam, the exact   */
+/* threshold).                                                              */
+/* ------------------------------------------------------------------------ */
+
+static int cmp_double(const void *a, const void *b)
+{
+    double x = *(const double *)a, y = *(const double *)b;
+    return (x > y) - (x < y);
+}
+
+int pmsref_median_filter(int W, int H, double *depth, double *normal, double *cost,
+                         const pmsref_params *p)
+{
+    if (!p || !depth || !normal || !cost) return -1;
+    int R = p->median_radius;
+    if (R <= 0) return 0;
+    long HW = (long)W * H;
+    double *copy = (double *)malloc(sizeof(double) * (size_t)HW);
+    char *drop = (char *)calloc((size_t)HW, 1);
+    double win[17 * 17];
+    if (!copy || !drop) {
+        free(copy);
+        free(drop);
+        return -20;
+    }
+    memcpy(copy, depth, sizeof(double) * (size_t)HW);
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            double d = copy[(long)y * W + x];
+            if (!(d > 0.0)) continue;
+            int n = 0;
+            for (int dy = -R; dy <= R; ++dy) {
+                int yy = y + dy;
+                if (yy < 0 || yy >= H) continue;
+                for (int dx = -R; dx <= R; ++dx) {
+                    int xx = ((x + dx) % W + W) % W;
+                    double v = copy[(long)yy * W + xx];
+                    if (v > 0.0) win[n++] = v;
+                }
+            }
+            qsort(win, (size_t)n, sizeof(double), cmp_double);
+            double m = win[(n - 1) / 2];
+            if (fabs(d - m) > p->median_rel * m) drop[(long)y * W + x] = 1;
+        }
+    for (long i = 0; i < HW; ++i)
+        if (drop[i]) {
+            depth[i] = 0.0;
+            normal[i] = normal[HW + i] = normal[2 * HW + i] = 0.0;
+            cost[i] = 2.0;
+        }
+    free(copy);
+    free(drop);
     return 0;
 }

@@ -57,6 +57,8 @@ typedef struct {
     double geo_rel_depth; /* relative depth threshold                     */
     int32_t geo_min_views; /* views that must agree; 0 => min(2, #maps)   */
     uint64_t seed;
+    int32_t median_radius; /* median post-filter window radius; 0 = off   */
+    double median_rel;     /* drop where |d - median| > median_rel * median */
 } pmsref_params;
 
 /* Fill the default parameters (11x11 patch sampled every 2nd pixel,
@@ -166,6 +168,16 @@ int pmsref_densify(int W, int H, const double *ref, int n_views,
                    const pmsref_pose *map_poses, double *depth_out,
                    double *normal_out, double *cost_out, int n_threads,
                    uint64_t order_seed);
+
+/* --- median post-filter (Sec. III-C, item 2) -------------------------------
+   A median-filtered copy of the depth map is compared with the map: where a
+   valid depth deviates from the median of the valid depths in its
+   (2 median_radius + 1)^2 window (longitude wrapping, rows beyond the image
+   left out; the lower median for an even count) by more than median_rel
+   times that median, the pixel is removed (depth 0, normal 0, cost 2).
+   Decisions use the unfiltered map only. No-op for median_radius 0. */
+int pmsref_median_filter(int W, int H, double *depth, double *normal, double *cost,
+                         const pmsref_params *p);
 
 /* --- plane-map warping (Sec. III-B) ------------------------------------------
    Carries the plane map (src_depth H*W, 0 = none; src_normal 3*H*W planar)

@@ -180,6 +180,7 @@ BASE_PARAMS = dict(
     refine_sigma_normal0=1.0, refine_normal_shrink=0.5,
     offsets=[(-3, 0), (3, 0), (0, -3), (0, 3), (-5, 0), (5, 0), (0, -5), (0, 5)],
     geo_px=1.0, geo_rel_depth=0.01, geo_min_views=0, seed=0,
+    median_radius=0, median_rel=0.05,
 )
 
 
