@@ -111,6 +111,8 @@ def lib() -> C.CDLL:
                                             _D, _D, _D, C.c_int, C.c_int, C.c_int, C.c_int,
                                             _D, _D, _D, C.c_int]
         L.pmsref_pixel_valid.argtypes = [C.c_int, C.c_int, C.POINTER(Params), C.c_int, C.c_int]
+        L.pmsref_view_filter.argtypes = [_D, _D, _D, C.c_long, C.c_double, C.c_double, C.c_double,
+                                         C.POINTER(C.c_long), C.POINTER(C.c_long)]
         L.pmsref_median_filter.argtypes = [C.c_int, C.c_int, _D, _D, _D, C.POINTER(Params)]
         L.pmsref_warp_planes.argtypes = [C.c_int, C.c_int, _D, _D, C.POINTER(Pose), C.POINTER(Pose),
                                          C.POINTER(Params), _D, _D]
@@ -422,3 +424,15 @@ def median_filter(depth, normal, cost, params: dict):
     if rc:
         raise ValueError(f"pmsref_median_filter failed: {rc}")
     return depth, normal, cost
+
+
+def view_filter(centre_a, centre_b, points, min_deg=6.0, max_deg=60.0, min_frac=0.2):
+    """Eq. (1): (accepted, points in the angle range, points counted)."""
+    ca, cb = _f64(centre_a).reshape(3), _f64(centre_b).reshape(3)
+    pts = _f64(points).reshape(-1, 3)
+    k, c = C.c_long(), C.c_long()
+    rc = lib().pmsref_view_filter(_dptr(ca), _dptr(cb), _dptr(pts) if len(pts) else None, len(pts),
+                                  float(min_deg), float(max_deg), float(min_frac), C.byref(k), C.byref(c))
+    if rc < 0:
+        raise ValueError(f"pmsref_view_filter failed: {rc}")
+    return bool(rc), k.value, c.value

@@ -1061,3 +1061,36 @@ int pmsref_median_filter(int W, int H, double *depth, double *normal, double *co
     free(drop);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* view filter (Sec. III-A, Eq. 1): the triangulation angle theta_p at each  */
+/* sparse point p seen by both keyframes, between the directions from p to  */
+/* the two camera centres; the candidate keyframe is accepted when at least */
+/* min_frac of the points have theta_p within [min_deg, max_deg]. Points at */
+/* a camera centre have no angle and are not counted. Parity: pinned by     */
+/* tests (points on the perpendicular bisector with closed-form angles,     */
+/* collinear points, mixtures with known fractions).                         */
+/* ------------------------------------------------------------------------ */
+
+int pmsref_view_filter(const double ca[3], const double cb[3], const double *points, long n,
+                       double min_deg, double max_deg, double min_frac, long *in_range,
+                       long *counted)
+{
+    if (!ca || !cb || (n > 0 && !points) || n < 0 || !in_range || !counted) return -1;
+    long k = 0, c = 0;
+    for (long i = 0; i < n; ++i) {
+        const double *p = points + 3 * i;
+        double a[3] = {ca[0] - p[0], ca[1] - p[1], ca[2] - p[2]};
+        double b[3] = {cb[0] - p[0], cb[1] - p[1], cb[2] - p[2]};
+        double la = sqrt(dot3(a, a)), lb = sqrt(dot3(b, b));
+        if (!(la > 0.0) || !(lb > 0.0)) continue;
+        double cs = dot3(a, b) / (la * lb);
+        cs = cs > 1.0 ? 1.0 : (cs < -1.0 ? -1.0 : cs);
+        double deg = acos(cs) * 180.0 / PI;
+        ++c;
+        if (deg >= min_deg && deg <= max_deg) ++k;
+    }
+    *in_range = k;
+    *counted = c;
+    return c > 0 && (double)k >= min_frac * (double)c;
+}

@@ -169,6 +169,16 @@ int pmsref_densify(int W, int H, const double *ref, int n_views,
                    double *normal_out, double *cost_out, int n_threads,
                    uint64_t order_seed);
 
+/* --- view filter (Sec. III-A, Eq. 1) ----------------------------------------
+   Camera centres ca, cb (world) and n world points (3n doubles, seen by
+   both keyframes). Counts the points whose angle between the directions to
+   the two centres lies in [min_deg, max_deg] (in_range) among the points
+   not at a centre (counted). Returns 1 to accept the keyframe (counted > 0
+   and in_range >= min_frac * counted), 0 to reject, negative on error. */
+int pmsref_view_filter(const double ca[3], const double cb[3], const double *points, long n,
+                       double min_deg, double max_deg, double min_frac, long *in_range,
+                       long *counted);
+
 /* --- median post-filter (Sec. III-C, item 2) -------------------------------
    A median-filtered copy of the depth map is compared with the map: where a
    valid depth deviates from the median of the valid depths in its
