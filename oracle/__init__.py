@@ -111,6 +111,12 @@ def lib() -> C.CDLL:
                                             _D, _D, _D, C.c_int, C.c_int, C.c_int, C.c_int,
                                             _D, _D, _D, C.c_int]
         L.pmsref_pixel_valid.argtypes = [C.c_int, C.c_int, C.POINTER(Params), C.c_int, C.c_int]
+        _U8 = C.POINTER(C.c_uint8)
+        L.pmsref_fuse.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(_D), C.POINTER(Pose), C.c_double,
+                                  _U8, C.POINTER(C.c_long)]
+        L.pmsref_coverage.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(_D), C.POINTER(Pose), _U8,
+                                      C.POINTER(Pose), C.c_int, C.c_int, _U8]
+        L.pmsref_coverage.restype = C.c_long
         L.pmsref_view_filter.argtypes = [_D, _D, _D, C.c_long, C.c_double, C.c_double, C.c_double,
                                          C.POINTER(C.c_long), C.POINTER(C.c_long)]
         L.pmsref_median_filter.argtypes = [C.c_int, C.c_int, _D, _D, _D, C.POINTER(Params)]
@@ -436,3 +442,32 @@ def view_filter(centre_a, centre_b, points, min_deg=6.0, max_deg=60.0, min_frac=
     if rc < 0:
         raise ValueError(f"pmsref_view_filter failed: {rc}")
     return bool(rc), k.value, c.value
+
+
+def fuse(depths, poses, voxel: float):
+    """Keep masks (n_maps, H, W) uint8 of the de-duplicated points and their count."""
+    M = _Views(depths)
+    H, W = M.arrs[0].shape
+    keep = np.zeros((len(M.arrs), H, W), dtype=np.uint8)
+    n = C.c_long()
+    rc = lib().pmsref_fuse(W, H, len(M.arrs), M.ptrs, _poses(poses), float(voxel),
+                           keep.ctypes.data_as(C.POINTER(C.c_uint8)), C.byref(n))
+    if rc:
+        raise ValueError(f"pmsref_fuse failed: {rc}")
+    return keep, n.value
+
+
+def coverage(depths, poses, keep, view_pose, Wc: int = 720, Hc: int = 360):
+    """(number of covered pixels, cover mask (Hc, Wc))."""
+    M = _Views(depths)
+    H, W = M.arrs[0].shape
+    cover = np.zeros((Hc, Wc), dtype=np.uint8)
+    kp = None
+    if keep is not None:
+        keep = np.ascontiguousarray(keep, dtype=np.uint8)
+        kp = keep.ctypes.data_as(C.POINTER(C.c_uint8))
+    c = lib().pmsref_coverage(W, H, len(M.arrs), M.ptrs, _poses(poses), kp, _poses([view_pose]),
+                              Wc, Hc, cover.ctypes.data_as(C.POINTER(C.c_uint8)))
+    if c < 0:
+        raise ValueError(f"pmsref_coverage failed: {c}")
+    return c, cover

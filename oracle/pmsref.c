@@ -1094,3 +1094,100 @@ int pmsref_view_filter(const double ca[3], const double cb[3], const double *poi
     *counted = c;
     return c > 0 && (double)k >= min_frac * (double)c;
 }
+
+/* ------------------------------------------------------------------------ */
+/* dense point-cloud fusion (Sec. III: the point-cloud thread buffers four  */
+/* consistent keyframes, erases duplicates and adds the points to the      */
+/* map). Reading: every valid pixel of the buffered depth maps is a world  */
+/* point; points falling into the same cubic voxel of edge `voxel` are      */
+/* duplicates, of which the first in (map, pixel) order is kept. Parity:    */
+/* pinned by tests (duplicate maps, brute force with numpy's unique, one    */
+/* huge voxel, coverage of analytic point sets).                            */
+/* ------------------------------------------------------------------------ */
+
+static void world_point(int W, int H, const pmsref_pose *pose, int x, int y, double d, double Xw[3])
+{
+    double b[3], Xc[3];
+    pmsref_unproject(W, H, x, y, b);
+    for (int k = 0; k < 3; ++k) Xc[k] = d * b[k] - pose->t[k];
+    /* X_w = R^T (X_c - t) */
+    for (int k = 0; k < 3; ++k)
+        Xw[k] = pose->R[k] * Xc[0] + pose->R[3 + k] * Xc[1] + pose->R[6 + k] * Xc[2];
+}
+
+typedef struct {
+    int64_t v[3];
+    long order; /* map * H * W + pixel */
+} voxel_entry;
+
+static int cmp_voxel(const void *a, const void *b)
+{
+    const voxel_entry *p = (const voxel_entry *)a, *q = (const voxel_entry *)b;
+    for (int k = 0; k < 3; ++k)
+        if (p->v[k] != q->v[k]) return p->v[k] < q->v[k] ? -1 : 1;
+    return (p->order > q->order) - (p->order < q->order);
+}
+
+int pmsref_fuse(int W, int H, int n_maps, const double *const *depths, const pmsref_pose *poses,
+                double voxel, uint8_t *keep, long *n_kept)
+{
+    if (W < 2 || H < 1 || W != 2 * H || n_maps < 1 || !depths || !poses || !keep || !n_kept ||
+        !(voxel > 0.0))
+        return -1;
+    long HW = (long)W * H;
+    voxel_entry *e = (voxel_entry *)malloc(sizeof(voxel_entry) * (size_t)(HW * n_maps));
+    if (!e) return -20;
+    long n = 0;
+    memset(keep, 0, (size_t)(HW * n_maps));
+    for (int m = 0; m < n_maps; ++m)
+        for (long i = 0; i < HW; ++i) {
+            double d = depths[m][i];
+            if (!(d > 0.0)) continue;
+            double X[3];
+            world_point(W, H, &poses[m], (int)(i % W), (int)(i / W), d, X);
+            for (int k = 0; k < 3; ++k) e[n].v[k] = (int64_t)floor(X[k] / voxel);
+            e[n].order = (long)m * HW + i;
+            ++n;
+        }
+    qsort(e, (size_t)n, sizeof(voxel_entry), cmp_voxel);
+    long kept = 0;
+    for (long j = 0; j < n; ++j)
+        if (j == 0 || e[j].v[0] != e[j - 1].v[0] || e[j].v[1] != e[j - 1].v[1] || e[j].v[2] != e[j - 1].v[2]) {
+            keep[e[j].order] = 1;
+            ++kept;
+        }
+    free(e);
+    *n_kept = kept;
+    return 0;
+}
+
+/* Completeness of a point cloud seen from one camera (the paper renders
+   depth panoramas of the fused cloud at 720 x 360): every kept point of the
+   maps marks the pixel of a Wc x Hc equirectangular image at view_pose
+   nearest to its projection; returns the number of marked pixels. */
+long pmsref_coverage(int W, int H, int n_maps, const double *const *depths,
+                     const pmsref_pose *poses, const uint8_t *keep, const pmsref_pose *view_pose,
+                     int Wc, int Hc, uint8_t *cover)
+{
+    if (!depths || !poses || !view_pose || !cover || Wc < 2 || Hc < 1) return -1;
+    long HW = (long)W * H;
+    memset(cover, 0, (size_t)Wc * Hc);
+    for (int m = 0; m < n_maps; ++m)
+        for (long i = 0; i < HW; ++i) {
+            double d = depths[m][i];
+            if (!(d > 0.0) || (keep && !keep[(long)m * HW + i])) continue;
+            double X[3], Y[3], u, v;
+            world_point(W, H, &poses[m], (int)(i % W), (int)(i / W), d, X);
+            for (int k = 0; k < 3; ++k)
+                Y[k] = view_pose->R[3 * k] * X[0] + view_pose->R[3 * k + 1] * X[1] +
+                       view_pose->R[3 * k + 2] * X[2] + view_pose->t[k];
+            if (!(dot3(Y, Y) > 0.0)) continue;
+            pmsref_project(Wc, Hc, Y, &u, &v);
+            int xi = wrap_index(floor(u + 0.5), Wc);
+            int yi = clamp_index(floor(v + 0.5), Hc);
+            cover[(long)yi * Wc + xi] = 1;
+        }
+    long c = 0;
+    for (long j = 0; j < (long)Wc * Hc; ++j) c += cover[j];
+    return c;
+}

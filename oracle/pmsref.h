@@ -179,6 +179,21 @@ int pmsref_view_filter(const double ca[3], const double cb[3], const double *poi
                        double min_deg, double max_deg, double min_frac, long *in_range,
                        long *counted);
 
+/* --- dense point-cloud fusion (Sec. III, point-cloud thread) ----------------
+   Every pixel with depth > 0 of the n_maps W x H maps (camera poses[m]) is a
+   world point; of the points in one cubic voxel of edge `voxel` (floor of
+   each coordinate / voxel) the first in (map, pixel) order is kept:
+   keep[m * H * W + pixel] = 1 (n_maps * H * W bytes), *n_kept = their count.
+   Returns 0 or a negative code. */
+int pmsref_fuse(int W, int H, int n_maps, const double *const *depths, const pmsref_pose *poses,
+                double voxel, uint8_t *keep, long *n_kept);
+/* Completeness: every kept point (keep may be null: all) marks the nearest
+   pixel of a Wc x Hc equirectangular image at view_pose; cover (Wc*Hc
+   bytes) receives the marks; returns the number of marked pixels. */
+long pmsref_coverage(int W, int H, int n_maps, const double *const *depths,
+                     const pmsref_pose *poses, const uint8_t *keep, const pmsref_pose *view_pose,
+                     int Wc, int Hc, uint8_t *cover);
+
 /* --- median post-filter (Sec. III-C, item 2) -------------------------------
    A median-filtered copy of the depth map is compared with the map: where a
    valid depth deviates from the median of the valid depths in its

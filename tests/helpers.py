@@ -66,3 +66,23 @@ def random_hypotheses(w, seed, gt_mix=0.5):
     bad = (n * b).sum(0) >= 0
     n[:, bad] = -b[:, bad]
     return d.astype(np.float32), n.astype(np.float32)
+
+
+def world_points(w, k, n, seed):
+    """n world points of keyframe k's rendered surfaces (random pixels with
+    ground-truth depth lifted through the camera), float64 (n, 3)."""
+    rng = np.random.default_rng(seed)
+    d = w.gt_depth[k].astype(np.float64)
+    ys, xs = np.nonzero(d > 0)
+    pick = rng.choice(len(ys), size=min(n, len(ys)), replace=False)
+    b = bearings(w.W, w.H)[:, ys[pick], xs[pick]]
+    R, t = w.poses[k]
+    R = np.asarray(R, dtype=np.float64)
+    t = np.asarray(t, dtype=np.float64)
+    X = b * d[ys[pick], xs[pick]]
+    return (R.T @ (X - t[:, None])).T
+
+
+def centre(pose):
+    R, t = pose
+    return -np.asarray(R, dtype=np.float64).T @ np.asarray(t, dtype=np.float64)
