@@ -62,6 +62,37 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+KERNEL_SOURCES = ("paper_2211_16266_amd/csrc/pms_kernels.hpp", "paper_2211_16266_amd/csrc/pms.hip")
+COUNTER_SUMMARY = "profiles/halfsweep_hall_1920_hbm_counters.md"
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per half-sweep launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads
+    for a plain copy of known size), or None when the summary is missing or
+    was taken on other kernel sources."""
+    path = os.path.join(ROOT, COUNTER_SUMMARY)
+    if not os.path.exists(path):
+        return None
+    rec = None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("<!-- traffic "):
+                rec = json.loads(line[len("<!-- traffic "):].rsplit("-->", 1)[0])
+    if not rec or rec.get("kernel_sources") != kernel_source_hash():
+        return None
+    return rec
+
+
 def valid_pixels(W: int, H: int, params: dict) -> int:
     r = (params["patch_size"] - 1) // 2
     return W * max(0, H - 2 * r)
@@ -161,16 +192,21 @@ def batch_section(args, torch, pms, synth, pool, ctx) -> dict:
     torch.cuda.synchronize()
     t_batch = (time.perf_counter() - t0) / K
 
+    def one_by_one(jobs):
+        for jd in jobs[:2]:
+            pms.densify(jd.ref, jd.nbrs, jd.ref_pose, jd.nbr_poses, jd.params, out=jd.out, ctx=ctx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for jd in jobs:
+            pms.densify(jd.ref, jd.nbrs, jd.ref_pose, jd.nbr_poses, jd.params, out=jd.out, ctx=ctx)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
     # the plain FP32 form: the same jobs, FP32 images, one pms_densify each
     jobs32 = jobs_for(imgs32)
-    for jd in jobs32[:2]:
-        pms.densify(jd.ref, jd.nbrs, jd.ref_pose, jd.nbr_poses, jd.params, out=jd.out, ctx=ctx)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for jd in jobs32:
-        pms.densify(jd.ref, jd.nbrs, jd.ref_pose, jd.nbr_poses, jd.params, out=jd.out, ctx=ctx)
-    torch.cuda.synchronize()
-    t_plain = time.perf_counter() - t0
+    t_plain = one_by_one(jobs32)
+    # FP16 images one job at a time (separates storage from batching)
+    t_plain16 = one_by_one(jobs_for(imgs16))
 
     per_class = {}
     for W in (960, 1920, 2880):
@@ -196,6 +232,31 @@ def batch_section(args, torch, pms, synth, pool, ctx) -> dict:
             "fp16_vs_fp32_within_0.5pct": float(np.mean(agree)),
         }
     batch.close()
+
+    # where batching pays: keyframes too small to fill the GPU alone
+    small_pool = synth.mixed_pool(seed=args.seed + 1, widths=(480,), dtype="f32")
+    small_mix = synth.mixed_jobs({480: 32}, seed=args.seed + 1)
+    s32 = {480: [torch.from_numpy(a).to(dev) for a in small_pool[480].images]}
+    s16 = {480: [t.half() for t in s32[480]]}
+
+    def small_jobs(imgs):
+        out = []
+        for mj in small_mix:
+            w = small_pool[480]
+            out.append(pms.job(imgs[480][mj.ref], [imgs[480][k] for k in mj.nbrs], w.poses[mj.ref],
+                               [w.poses[k] for k in mj.nbrs], dict(w.params, seed=mj.seed)))
+        return out
+
+    small_batch = pms.Batch(small_jobs(s16), ctx=tune_ctx)
+    small_batch.run(graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        small_batch.run(graph=True)
+    torch.cuda.synchronize()
+    t_small_batch = (time.perf_counter() - t0) / K
+    small_batch.close()
+    t_small_plain = one_by_one(small_jobs(s32))
     tune_ctx.close()
     n = len(mix)
     return {"workload": "32 jobs: 12@960x480, 12@1920x960, 8@2880x1440, N~U{3..6}",
@@ -204,8 +265,13 @@ def batch_section(args, torch, pms, synth, pool, ctx) -> dict:
             "schedule": best,
             "keyframes_per_s": n / t_batch, "s_per_batch": t_batch,
             "plain_fp32_keyframes_per_s": n / t_plain, "plain_fp32_s": t_plain,
+            "plain_fp16_keyframes_per_s": n / t_plain16,
             "speedup_vs_plain_fp32": t_plain / t_batch,
-            "accuracy_per_class": per_class}
+            "accuracy_per_class": per_class,
+            "small_keyframes": {"workload": "32 jobs at 480x240, N~U{3..6}",
+                                "batched_fp16_keyframes_per_s": 32 / t_small_batch,
+                                "plain_fp32_keyframes_per_s": 32 / t_small_plain,
+                                "speedup": t_small_plain / t_small_batch}}
 
 
 def serving_section(args, torch, pms, synth, pool, ctx) -> dict:
@@ -256,6 +322,67 @@ def serving_section(args, torch, pms, synth, pool, ctx) -> dict:
             "solo_rerun_bitwise_equal": bool(solo_equal), "solo_rerun_checked": len(kept)}
 
 
+def counter_summary(fetch_dir: str, write_dir: str, probe_bytes: int, commands: list) -> str:
+    """Writes the HBM traffic summary of the half-sweep kernel from two
+    rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; csv) of this benchmark with
+    --copy-probe, each counter scaled by what it reads for the probe copy."""
+    import csv
+    import glob
+
+    def per_dispatch(d, counter):
+        rows = {}
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                if r["Counter_Name"] != counter:
+                    continue
+                key = (f, r["Dispatch_Id"])
+                name, val = r["Kernel_Name"], float(r["Counter_Value"])
+                rows[key] = (name, rows.get(key, (name, 0.0))[1] + val)
+        return list(rows.values())
+
+    out = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = per_dispatch(d, counter)
+        hs = [v for n, v in rows if "k_tiles<1," in n]
+        probe = max(v for n, v in rows if "pms::" not in n)
+        out[counter] = {"halfsweep_kib": sum(hs) / len(hs), "dispatches": len(hs),
+                        "probe_kib": probe, "scale": probe_bytes / 1024.0 / probe}
+    fetch = out["FETCH_SIZE"]["halfsweep_kib"] * out["FETCH_SIZE"]["scale"] * 1024
+    write = out["WRITE_SIZE"]["halfsweep_kib"] * out["WRITE_SIZE"]["scale"] * 1024
+    rec = {"kernel_sources": kernel_source_hash(), "bytes_per_launch": fetch + write,
+           "fetch_bytes": fetch, "write_bytes": write,
+           "fetch_kib_raw": out["FETCH_SIZE"]["halfsweep_kib"],
+           "write_kib_raw": out["WRITE_SIZE"]["halfsweep_kib"],
+           "fetch_scale": out["FETCH_SIZE"]["scale"], "write_scale": out["WRITE_SIZE"]["scale"],
+           "dispatches": out["FETCH_SIZE"]["dispatches"]}
+    lines = [
+        "# HBM traffic of the half-sweep kernel, hall_1920 (1920x960, 4 neighbours, 36-sample patch)",
+        "",
+        "Two rocprofv3 counter runs of the benchmark with a 256 MiB device copy run",
+        "once before the timed steps (the probe calibrates each counter):",
+        "",
+        *[f"    {c}" for c in commands],
+        "",
+        "| counter | half-sweep, KiB per dispatch (raw) | probe copy reads | scale | bytes per launch |",
+        "|---|---|---|---|---|",
+        f"| FETCH_SIZE | {rec['fetch_kib_raw']:.0f} | {out['FETCH_SIZE']['probe_kib']:.0f} KiB for "
+        f"{probe_bytes / 1024:.0f} KiB | {rec['fetch_scale']:.3f} | {fetch / 1e6:.1f} MB |",
+        f"| WRITE_SIZE | {rec['write_kib_raw']:.0f} | {out['WRITE_SIZE']['probe_kib']:.0f} KiB for "
+        f"{probe_bytes / 1024:.0f} KiB | {rec['write_scale']:.3f} | {write / 1e6:.1f} MB |",
+        "",
+        f"Traffic per half-sweep launch: {(fetch + write) / 1e6:.1f} MB over "
+        f"{rec['dispatches']} dispatches; kernel sources {rec['kernel_sources']} (the benchmark",
+        "reports this figure only while the sources hash the same).",
+        "",
+        "<!-- traffic " + json.dumps(rec) + " -->",
+        "",
+    ]
+    path = os.path.join(ROOT, COUNTER_SUMMARY)
+    with open(path, "w") as f:
+        f.write("\n".join(lines))
+    return path
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -275,7 +402,17 @@ def main() -> int:
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="bytes of a plain device-to-device copy run once before the "
                          "timed region, to calibrate HBM byte counters (0 = none)")
+    ap.add_argument("--counter-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the traffic summary from two rocprofv3 --pmc csv directories "
+                         "(no GPU needed) and exit")
     args = ap.parse_args()
+    if args.counter_summary:
+        cmd = ("rocprofv3 --pmc {c} --output-format csv -d gpurun_out/pmc_{c} -o pmc -- python3 "
+               "bench.py --steps 2 --warmup 0 --cpu-budget 0 --no-batch --serve-horizon 0 "
+               "--copy-probe 268435456")
+        print(counter_summary(*args.counter_summary, 268435456,
+                              [cmd.format(c="FETCH_SIZE"), cmd.format(c="WRITE_SIZE")]))
+        return 0
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the densifier runs one keyframe job per GPU "
               "and this build has no multi-GPU path; run with --gpus 1", file=sys.stderr)
@@ -363,6 +500,7 @@ def main() -> int:
     achieved = slots_per_launch / avg_half_s / 1e12
     img_bytes = (N + 1) * W * H * w.images[0].itemsize
     hbm_bytes = (vpx // 2) * HBM_BYTES_PER_UPDATE + img_bytes
+    traffic = measured_traffic()
 
     result = {
         "metric": METRIC,
@@ -395,7 +533,8 @@ def main() -> int:
             "peak": PEAK_TSLOTS,
             "unit": "T VALU lane-slots/s",
             "frac": achieved / PEAK_TSLOTS,
-            "traffic": None,
+            "traffic": traffic["bytes_per_launch"] if traffic else None,
+            "traffic_detail": traffic,
             "avg_launch_ms": avg_half_s * 1e3,
             "launches": n_half,
             "algorithmic_per_launch": {"ncc_evals": evals_per_launch, "slots": slots_per_launch,

@@ -109,6 +109,10 @@ typedef struct {
     double geo_rel_depth; /* consistency: relative range error bound       */
     int32_t geo_min_views; /* maps that must agree; 0 => min(2, #maps)     */
     uint64_t seed;        /* key of the counter-based RNG                   */
+    int32_t median_radius; /* median post-filter (Sec. III-C item 2): window
+                              (2r+1)^2, 0..8; 0 = off (default)             */
+    double median_rel;     /* removes depths deviating from the window's
+                              median by more than this fraction (0.05)      */
 } pms_params;
 
 typedef struct pms_context pms_context;
@@ -129,6 +133,14 @@ typedef struct {
     pms_plane depth_out;
     pms_plane normal_out[3];
     pms_plane cost_out;
+    /* Optional initial planes (Sec. III-B, plane-map warping: typically
+       pms_warp_planes of the previous keyframe's result). init_depth.data
+       == NULL means a random initialisation everywhere; otherwise the four
+       planes share one pitch, and at every valid pixel whose init depth lies
+       in [depth_min, depth_max] and whose normal faces the camera the
+       supplied plane replaces the random one. */
+    pms_plane init_depth;
+    pms_plane init_normal[3];
 } pms_job;
 
 /* Launch schedule of a context: the tile one 256-thread workgroup serves and
@@ -165,7 +177,11 @@ pms_status pms_context_destroy(pms_context *ctx);
 /* Densifies one reference keyframe (Sec. III and III-B/C):
    random initialisation, `iterations` red-black sweeps of propagation and
    random refinement scored by the plane-induced warp and NCC against
-   n_nbrs neighbours, and -- when n_maps > 0 -- the geometric-consistency
+   n_nbrs neighbours, the median post-filter when median_radius > 0 (a
+   valid depth is removed if it deviates from the lower median of the valid
+   depths of its window -- longitude wrapping, rows beyond the image left
+   out -- by more than median_rel times that median; decided on the
+   unfiltered map), and -- when n_maps > 0 -- the geometric-consistency
    filter against the depth maps of n_maps other keyframes (maps[k] is a
    W x H plane of ranges, 0 = no depth, for the camera at map_poses[k]).
    Writes depth_out, normal_out[0..2] (nx, ny, nz) and cost_out. */
@@ -272,6 +288,64 @@ pms_status pms_consistency(pms_context *ctx, int32_t width, int32_t height,
                            const pms_pose *map_poses, int32_t n_maps, const pms_params *params,
                            pms_plane depth_io, const pms_plane normal_io[3], pms_plane cost_io,
                            void *stream);
+
+/* Plane-map warping (Sec. III-B: the optimised plane map of the preceding
+   keyframe initialises the current one). Every valid pixel of the source
+   map (src_depth > 0, rows r .. H-1-r) carries its plane point into the
+   destination camera (relative pose composed in FP64) and claims the
+   destination pixel nearest to its projection; of several claims the
+   nearest point wins (its range rounded to float, ties to the lower source
+   pixel index, so the result does not depend on scheduling). The winning
+   plane -- normal rotated into the destination frame, through the moved
+   point -- is re-intersected with the destination pixel's own ray and kept
+   if it faces the camera with a depth in [depth_min, depth_max]. Writes
+   dst_depth (0 where no plane arrives) and dst_normal (0 there). Both maps
+   are width x height (width == 2 height); src and dst planes must not
+   overlap. Uses 8 bytes per pixel of context scratch. */
+pms_status pms_warp_planes(pms_context *ctx, int32_t width, int32_t height,
+                           const pms_pose *src_pose, pms_plane src_depth,
+                           const pms_plane src_normal[3], const pms_pose *dst_pose,
+                           const pms_params *params, pms_plane dst_depth,
+                           const pms_plane dst_normal[3], void *stream);
+
+/* View filter (Sec. III-A, Eq. 1): for n_points sparse world points
+   (device memory, 3 doubles each, points seen by both keyframes) counts
+   those whose angle between the directions to the two camera centres
+   centre_a and centre_b (world, host) lies in [min_deg, max_deg]
+   (counts_out[0]) and those not at a centre (counts_out[1]); counts_out is
+   two uint64 in device memory, overwritten. The keyframe is accepted when
+   counts_out[0] >= 0.2 counts_out[1] (the paper's 20%, 6 and 60 degrees).
+   Angles in FP64. */
+pms_status pms_view_filter(pms_context *ctx, const double centre_a[3], const double centre_b[3],
+                           const double *points, int64_t n_points, double min_deg,
+                           double max_deg, uint64_t *counts_out, void *stream);
+
+/* Dense point-cloud fusion (Sec. III: the point-cloud thread buffers four
+   consistent keyframes and erases duplicate points). Every pixel with depth
+   > 0 of the n_maps (1 .. PMS_MAX_MAPS) width x height depth planes, taken
+   at poses[m], is a world point; of the points in one cubic voxel of edge
+   `voxel` metres (floor of each world coordinate / voxel) the first in
+   (map, pixel) order is kept. Writes keep_out[m * H * W + y * W + x] = 1
+   for kept points, else 0 (device, n_maps * H * W bytes) and the number of
+   kept points to n_kept_out (device uint64). Voxel coordinates must lie
+   within +-2^20 (points beyond are not kept). Uses 16 bytes of context
+   scratch per slot of a hash table of at least 2 n_maps W H slots. The
+   result does not depend on scheduling. */
+pms_status pms_fuse(pms_context *ctx, int32_t width, int32_t height, int32_t n_maps,
+                    const pms_plane *depths, const pms_pose *poses, double voxel,
+                    uint8_t *keep_out, uint64_t *n_kept_out, void *stream);
+
+/* Completeness of fused points seen from one camera (the paper renders
+   depth panoramas of the cloud at 720 x 360): every point of the maps (as
+   in pms_fuse) whose keep byte is set (keep == NULL: every point) marks the
+   pixel of an out_width x out_height equirectangular image at view_pose
+   nearest to its projection. Writes cover_out (device, out_width *
+   out_height bytes, 1 = marked) and the number of marked pixels to
+   n_covered_out (device uint64). */
+pms_status pms_coverage(pms_context *ctx, int32_t width, int32_t height, int32_t n_maps,
+                        const pms_plane *depths, const pms_pose *poses, const uint8_t *keep,
+                        const pms_pose *view_pose, int32_t out_width, int32_t out_height,
+                        uint8_t *cover_out, uint64_t *n_covered_out, void *stream);
 
 /* Philox4x64-10 blocks for counters (ctr0 + i, 0, 0, 0), i < n, with key
    (key0, key1), written to the device buffer out[4n] -- the generator the

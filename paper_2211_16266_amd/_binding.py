@@ -57,7 +57,7 @@ class Params(C.Structure):
         ("refine_sigma_normal0", C.c_double), ("refine_normal_shrink", C.c_double),
         ("n_offsets", C.c_int32), ("offsets", (C.c_int32 * 2) * MAX_OFFSETS),
         ("geo_px", C.c_double), ("geo_rel_depth", C.c_double), ("geo_min_views", C.c_int32),
-        ("seed", C.c_uint64),
+        ("seed", C.c_uint64), ("median_radius", C.c_int32), ("median_rel", C.c_double),
     ]
 
 
@@ -66,7 +66,7 @@ class Job(C.Structure):
                 ("nbr_poses", C.POINTER(Pose)), ("n_nbrs", C.c_int32),
                 ("maps", C.POINTER(Plane)), ("map_poses", C.POINTER(Pose)), ("n_maps", C.c_int32),
                 ("params", C.POINTER(Params)), ("depth_out", Plane), ("normal_out", Plane * 3),
-                ("cost_out", Plane)]
+                ("cost_out", Plane), ("init_depth", Plane), ("init_normal", Plane * 3)]
 
 
 class Schedule(C.Structure):
@@ -98,6 +98,15 @@ def lib() -> C.CDLL:
                                     C.c_void_p]
         L.pms_consistency.argtypes = [C.c_void_p, C.c_int32, C.c_int32, P(Pose), P(Plane), P(Pose),
                                       C.c_int32, P(Params), Plane, P(Plane), Plane, C.c_void_p]
+        L.pms_warp_planes.argtypes = [C.c_void_p, C.c_int32, C.c_int32, P(Pose), Plane, P(Plane),
+                                      P(Pose), P(Params), Plane, P(Plane), C.c_void_p]
+        L.pms_fuse.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, P(Plane), P(Pose), C.c_double,
+                               C.c_void_p, C.c_void_p, C.c_void_p]
+        L.pms_coverage.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, P(Plane), P(Pose),
+                                   C.c_void_p, P(Pose), C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                   C.c_void_p]
+        L.pms_view_filter.argtypes = [C.c_void_p, P(C.c_double), P(C.c_double), C.c_void_p, C.c_int64,
+                                      C.c_double, C.c_double, C.c_void_p, C.c_void_p]
         L.pms_philox_stream.argtypes = [C.c_void_p, C.c_uint64, C.c_uint64, C.c_uint64, C.c_int64,
                                         C.c_void_p, C.c_void_p]
         L.pms_profile_enable.argtypes = [C.c_void_p, C.c_int32]
@@ -128,7 +137,8 @@ def lib() -> C.CDLL:
                      "pms_densify_batch", "pms_batch_create", "pms_batch_run", "pms_batch_bytes",
                      "pms_batch_destroy", "pms_get_schedule", "pms_set_schedule", "pms_autotune",
                      "pms_server_create", "pms_server_submit", "pms_server_step",
-                     "pms_server_poll", "pms_server_stats", "pms_server_destroy"):
+                     "pms_server_poll", "pms_server_stats", "pms_server_destroy",
+                     "pms_warp_planes", "pms_view_filter", "pms_fuse", "pms_coverage"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -370,6 +380,83 @@ def consistency(ref_pose, maps, map_poses, params: dict | None, depth: torch.Ten
     ctx.check(st, "pms_consistency")
 
 
+def warp_planes(src_depth: torch.Tensor, src_normal: torch.Tensor, src_pose, dst_pose,
+                params: dict | None = None, out=None, ctx: Context | None = None, stream=None):
+    """The plane map (depth (H, W), normal (3, H, W)) of the keyframe at
+    src_pose carried into the keyframe at dst_pose (Sec. III-B)."""
+    ctx = ctx or default_context(src_depth.device.index or 0)
+    H, W = src_depth.shape
+    if out is None:
+        out = (torch.empty((H, W), dtype=torch.float32, device=src_depth.device),
+               torch.empty((3, H, W), dtype=torch.float32, device=src_depth.device))
+    dd, dn = out
+    st = lib().pms_warp_planes(ctx.handle, W, H, C.byref(make_pose(src_pose)),
+                               make_plane(src_depth, "src depth"), _planes3(src_normal, "src normal"),
+                               C.byref(make_pose(dst_pose)), C.byref(make_params(params)),
+                               make_plane(dd, "dst depth"), _planes3(dn, "dst normal"),
+                               C.c_void_p(_stream_handle(stream)))
+    ctx.check(st, "pms_warp_planes")
+    return dd, dn
+
+
+def view_filter(centre_a, centre_b, points: torch.Tensor, min_deg: float = 6.0,
+                max_deg: float = 60.0, min_frac: float = 0.2, ctx: Context | None = None,
+                stream=None):
+    """Eq. (1) on device points (n, 3) float64: (accepted, in range,
+    counted). Synchronises the stream to read the two counts."""
+    ctx = ctx or default_context(points.device.index or 0)
+    if points.dtype != torch.float64 or points.dim() != 2 or points.shape[1] != 3 or not points.is_cuda:
+        raise ValueError("points must be a (n, 3) float64 device tensor")
+    pts = points.contiguous()
+    counts = torch.empty(2, dtype=torch.int64, device=points.device)
+    ca = (C.c_double * 3)(*[float(v) for v in centre_a])
+    cb = (C.c_double * 3)(*[float(v) for v in centre_b])
+    st = lib().pms_view_filter(ctx.handle, ca, cb, C.c_void_p(pts.data_ptr()), pts.shape[0],
+                               float(min_deg), float(max_deg), C.c_void_p(counts.data_ptr()),
+                               C.c_void_p(_stream_handle(stream)))
+    ctx.check(st, "pms_view_filter")
+    k, c = [int(v) for v in counts.cpu().tolist()]
+    return (c > 0 and k >= min_frac * c), k, c
+
+
+def fuse(depths, poses, voxel: float, ctx: Context | None = None, stream=None):
+    """Voxel de-duplication of the points of the depth maps (Sec. III):
+    (keep (n_maps, H, W) uint8 device tensor, number of kept points)."""
+    ctx = ctx or default_context(depths[0].device.index or 0)
+    H, W = depths[0].shape
+    dp = (Plane * len(depths))(*[make_plane(d, "depth map") for d in depths])
+    keep = torch.empty((len(depths), H, W), dtype=torch.uint8, device=depths[0].device)
+    n = torch.empty(1, dtype=torch.int64, device=depths[0].device)
+    st = lib().pms_fuse(ctx.handle, W, H, len(depths), dp, _poses(poses), float(voxel),
+                        C.c_void_p(keep.data_ptr()), C.c_void_p(n.data_ptr()),
+                        C.c_void_p(_stream_handle(stream)))
+    ctx.check(st, "pms_fuse")
+    return keep, int(n.item())
+
+
+def coverage(depths, poses, keep, view_pose, out_width: int = 720, out_height: int = 360,
+             ctx: Context | None = None, stream=None):
+    """Pixels of an out_width x out_height panorama at view_pose marked by
+    the kept points: (count, cover (out_height, out_width) uint8 tensor)."""
+    ctx = ctx or default_context(depths[0].device.index or 0)
+    H, W = depths[0].shape
+    dp = (Plane * len(depths))(*[make_plane(d, "depth map") for d in depths])
+    cover = torch.empty((out_height, out_width), dtype=torch.uint8, device=depths[0].device)
+    n = torch.empty(1, dtype=torch.int64, device=depths[0].device)
+    st = lib().pms_coverage(ctx.handle, W, H, len(depths), dp, _poses(poses),
+                            C.c_void_p(keep.data_ptr()) if keep is not None else None,
+                            C.byref(make_pose(view_pose)), out_width, out_height,
+                            C.c_void_p(cover.data_ptr()), C.c_void_p(n.data_ptr()),
+                            C.c_void_p(_stream_handle(stream)))
+    ctx.check(st, "pms_coverage")
+    return int(n.item()), cover
+
+
+def densify_job(jd: "JobDesc", ctx: Context | None = None, stream=None):
+    """One job (with its optional initial planes) through the batch path."""
+    return densify_batch([jd], ctx=ctx, stream=stream)[0]
+
+
 def philox_stream(key0: int, key1: int, ctr0: int, n: int, device: int = 0,
                   ctx: Context | None = None, stream=None) -> torch.Tensor:
     """(n, 4) int64 tensor holding the uint64 Philox4x64-10 blocks."""
@@ -390,7 +477,8 @@ class JobDesc:
     ``out`` = (depth, normal, cost) tensors; allocated when omitted."""
 
     def __init__(self, ref, nbrs, ref_pose, nbr_poses, params=None, maps=None, map_poses=None,
-                 out=None):
+                 out=None, init=None):
+        self.init = init  # optional (depth (H, W), normal (3, H, W)) initial planes
         self.ref, self.nbrs = ref, list(nbrs)
         self.ref_pose, self.nbr_poses = ref_pose, list(nbr_poses)
         self.params = params
@@ -407,8 +495,9 @@ class JobDesc:
         self.out = out
 
 
-def job(ref, nbrs, ref_pose, nbr_poses, params=None, maps=None, map_poses=None, out=None) -> JobDesc:
-    return JobDesc(ref, nbrs, ref_pose, nbr_poses, params, maps, map_poses, out)
+def job(ref, nbrs, ref_pose, nbr_poses, params=None, maps=None, map_poses=None, out=None,
+        init=None) -> JobDesc:
+    return JobDesc(ref, nbrs, ref_pose, nbr_poses, params, maps, map_poses, out, init)
 
 
 def _job_array(jobs):
@@ -436,6 +525,11 @@ def _job_array(jobs):
         for k in range(3):
             arr[i].normal_out[k] = make_plane(normal[k], "normal")
         arr[i].cost_out = make_plane(cost, "cost")
+        if jd.init is not None:
+            idp, inn = jd.init
+            arr[i].init_depth = make_plane(idp, "init depth")
+            for k in range(3):
+                arr[i].init_normal[k] = make_plane(inn[k], "init normal")
         keep += [nb, npz, mp, mpz, prm]
     return arr, keep
 

@@ -29,11 +29,13 @@
 
 namespace {
 
-constexpr int kNumKernelKinds = 8;
+constexpr int kNumKernelKinds = 11;
 const char *const kKernelNames[kNumKernelKinds] = {"refstats", "init", "halfsweep", "finalize",
-                                                   "consistency", "eval", "io", "batch"};
+                                                   "consistency", "eval", "io", "batch", "warp",
+                                                   "median", "fuse"};
 enum KernelKind {
-    KK_REFSTATS, KK_INIT, KK_HALFSWEEP, KK_FINALIZE, KK_CONSISTENCY, KK_EVAL, KK_IO, KK_GRAPH
+    KK_REFSTATS, KK_INIT, KK_HALFSWEEP, KK_FINALIZE, KK_CONSISTENCY, KK_EVAL, KK_IO, KK_GRAPH, KK_WARP,
+    KK_MEDIAN, KK_FUSE
 };
 
 struct TimedLaunch {
@@ -159,6 +161,9 @@ bool check_params(pms_context *ctx, const pms_params *p, int W, int H, int n_vie
     }
     if (!(p->geo_px >= 0.0) || !(p->geo_rel_depth >= 0.0) || p->geo_min_views < 0)
         return bad("bad consistency thresholds");
+    if (p->median_radius < 0 || p->median_radius > 8 || !(p->median_rel >= 0.0) ||
+        !std::isfinite(p->median_rel))
+        return bad("median_radius must be in [0, 8] and median_rel >= 0");
     return true;
 }
 
@@ -273,7 +278,9 @@ pms::ViewPoseF relative_pose(const pms_pose &ref, const pms_pose &nbr)
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-size_t pad_elem_size(int dtype) { return dtype == PMS_F16 ? 2 : 4; }
+// Bytes per position of a re-laid-out image: (value, difference to the next
+// column) in FP32 whatever the input type.
+size_t pad_elem_size(int) { return sizeof(float2); }
 
 pms_status set_device(pms_context *ctx)
 {
@@ -402,6 +409,7 @@ struct JobSpec {
     const pms_params *p = nullptr;
     pms_plane depth{}, normal[3]{}, cost{};  // outputs, or in/out planes
     pms_plane depth_in{}, normal_in[3]{};    // MODE_EVAL hypotheses
+    pms_plane init_depth{}, init_normal[3]{};  // MODE_DENSIFY initial planes (optional)
     const pms_plane *per_view = nullptr;     // MODE_EVAL, nullable
     int iteration = 0, colour = 0;           // MODE_SWEEP
 };
@@ -442,7 +450,7 @@ struct Rec {
     Variant v;
     size_t entry_off;
     int n_entries;
-    int total;
+    int total;  // workgroup slots per XCD (the grid is 8 x total)
     int job, colour;
 };
 
@@ -454,7 +462,7 @@ struct Plan {
     size_t off_pads = 0, off_entries = 0, args_bytes = 0, total_bytes = 0;
 };
 
-// Appends a launch over (job, blocks, iteration, colour) items.
+// Appends a launch over (job, tiles, iteration, colour) items.
 void add_rec(Plan &P, int kind, int sub, int dtype, Variant v,
              const std::vector<std::tuple<int, int, int, int>> &items)
 {
@@ -466,17 +474,18 @@ void add_rec(Plan &P, int kind, int sub, int dtype, Variant v,
     R.entry_off = P.entries.size();
     int first = 0;
     for (auto &it : items) {
-        const int blocks = std::get<1>(it);
-        if (blocks <= 0) continue;
-        P.entries.push_back({std::get<0>(it), first, std::get<2>(it), std::get<3>(it)});
-        first += blocks;
+        const int tiles = std::get<1>(it);
+        if (tiles <= 0) continue;
+        const int per_xcd = (tiles + 7) / 8;
+        P.entries.push_back({std::get<0>(it), first, tiles, per_xcd, std::get<2>(it), std::get<3>(it)});
+        first += per_xcd;
     }
     R.n_entries = (int)(P.entries.size() - R.entry_off);
     if (R.n_entries == 0) {
         P.entries.resize(R.entry_off);
         return;
     }
-    P.entries.push_back({-1, first, 0, 0});
+    P.entries.push_back({-1, first, 0, 0, 0, 0});
     R.total = first;
     P.recs.push_back(R);
 }
@@ -502,7 +511,7 @@ void fill_sweep_args(pms::SweepArgs &A, const JobSpec &J, const Geometry &g, con
     A.inv_P = (float)(1.0 / A.P);
     A.n_views = J.n_nbrs;
     A.top_k = p->top_k > 0 ? p->top_k : (J.n_nbrs + 1) / 2;
-    A.k_float = (float)A.top_k;
+    A.inv_k = (float)(1.0 / A.top_k);
     A.var_floor = (float)p->ncc_var_floor;
     A.dmin = (float)p->depth_min;
     A.dmax = (float)p->depth_max;
@@ -548,6 +557,13 @@ void fill_sweep_args(pms::SweepArgs &A, const JobSpec &J, const Geometry &g, con
     A.tab_col = T.col;
     A.tab_row64 = T.row64;
     A.tab_col64 = T.col64;
+    if (J.mode == MODE_DENSIFY && J.init_depth.data) {
+        A.init_depth = J.init_depth.data;
+        A.init_n0 = J.init_normal[0].data;
+        A.init_n1 = J.init_normal[1].data;
+        A.init_n2 = J.init_normal[2].data;
+        A.init_pitch = J.init_depth.pitch_elems;
+    }
 }
 
 void fill_io(pms::IoArgs &io, const JobSpec &J, int r, float4 *state, float *cost)
@@ -567,6 +583,8 @@ void fill_io(pms::IoArgs &io, const JobSpec &J, int r, float4 *state, float *cos
     io.pn1 = J.normal[1].pitch_elems;
     io.pn2 = J.normal[2].pitch_elems;
     io.pc = J.cost.pitch_elems;
+    io.median_radius = J.p->median_radius;
+    io.median_rel = J.p->median_rel;
 }
 
 void fill_geo(pms::GeoArgs &G, const JobSpec &J, int r, const Tables &T)
@@ -712,6 +730,13 @@ pms_status build_plan(pms_context *ctx, const std::vector<JobSpec> &specs, char 
                 items.emplace_back(i, (int)blocks_of((long long)specs[i].W * specs[i].H), 0, 0);
         add_rec(P, KK_FINALIZE, 0, 0, none, items);
     }
+    {
+        Items items;
+        for (int i = 0; i < n; ++i)
+            if (specs[i].mode == MODE_DENSIFY && specs[i].p->median_radius > 0)
+                items.emplace_back(i, (int)blocks_of((long long)specs[i].W * specs[i].H), 0, 0);
+        add_rec(P, KK_MEDIAN, 0, 0, none, items);
+    }
     for (int i = 0; i < n; ++i)
         if (specs[i].mode == MODE_SWEEP) {
             Rec R{};
@@ -856,8 +881,8 @@ pms_status enqueue_plan(pms_context *ctx, const Plan &P, char *dev, hipStream_t 
             L.table = R.kind == KK_IO ? static_cast<const void *>(dev + P.off_pads) : static_cast<const void *>(dev);
             L.entries = reinterpret_cast<const pms::Entry *>(dev + P.off_entries) + R.entry_off;
             L.n_entries = R.n_entries;
-            L.per_xcd = (R.total + 7) / 8;
-            dim3 grid(8u * (unsigned)L.per_xcd);
+            L.slots = R.total;
+            dim3 grid(8u * (unsigned)L.slots);
             switch (R.kind) {
             case KK_IO: hipLaunchKernelGGL(pms::k_pad, grid, dim3(pms::BLOCK), 0, s, L); break;
             case KK_REFSTATS: hipLaunchKernelGGL(pms::k_refstats, grid, dim3(pms::BLOCK), 0, s, L); break;
@@ -865,6 +890,7 @@ pms_status enqueue_plan(pms_context *ctx, const Plan &P, char *dev, hipStream_t 
             case KK_HALFSWEEP: launch_tiles<pms::TK_HALFSWEEP>(R.dtype, R.v, L, grid, s); break;
             case KK_EVAL: launch_tiles<pms::TK_EVAL>(R.dtype, R.v, L, grid, s); break;
             case KK_FINALIZE: hipLaunchKernelGGL(pms::k_finalize, grid, dim3(pms::BLOCK), 0, s, L); break;
+            case KK_MEDIAN: hipLaunchKernelGGL(pms::k_median, grid, dim3(pms::BLOCK), 0, s, L); break;
             case KK_CONSISTENCY: hipLaunchKernelGGL(pms::k_consistency, grid, dim3(pms::BLOCK), 0, s, L); break;
             default: break;
             }
@@ -980,9 +1006,23 @@ bool densify_spec(pms_context *ctx, const pms_image *ref, const pms_pose *ref_po
 
 bool job_spec(pms_context *ctx, const pms_job &jb, JobSpec &J, pms_status *st)
 {
-    return densify_spec(ctx, &jb.ref, &jb.ref_pose, jb.nbrs, jb.nbr_poses, jb.n_nbrs, jb.maps,
-                        jb.map_poses, jb.n_maps, jb.params, jb.depth_out, jb.normal_out,
-                        jb.cost_out, J, st);
+    if (!densify_spec(ctx, &jb.ref, &jb.ref_pose, jb.nbrs, jb.nbr_poses, jb.n_nbrs, jb.maps,
+                      jb.map_poses, jb.n_maps, jb.params, jb.depth_out, jb.normal_out,
+                      jb.cost_out, J, st))
+        return false;
+    if (jb.init_depth.data) {
+        const int W = jb.ref.width;
+        if (!check_outputs(ctx, W, jb.init_depth, jb.init_normal, jb.init_depth, st)) return false;
+        const int64_t pitch = jb.init_depth.pitch_elems;
+        for (int k = 0; k < 3; ++k)
+            if (jb.init_normal[k].pitch_elems != pitch) {
+                *st = fail(ctx, PMS_ERR_INVALID_ARG, "init_depth and init_normal must share one pitch");
+                return false;
+            }
+        J.init_depth = jb.init_depth;
+        for (int k = 0; k < 3; ++k) J.init_normal[k] = jb.init_normal[k];
+    }
+    return true;
 }
 
 // Output planes of one batch must not be read as another job's consistency
@@ -1001,13 +1041,23 @@ bool check_batch_aliasing(pms_context *ctx, const std::vector<JobSpec> &specs, p
         *st = fail(ctx, PMS_ERR_INVALID_ARG, "two output planes of a batch share one buffer");
         return false;
     }
-    for (auto &J : specs)
+    for (auto &J : specs) {
         for (int k = 0; k < J.n_maps; ++k)
             if (std::binary_search(sorted.begin(), sorted.end(), (const float *)J.maps[k].data)) {
                 *st = fail(ctx, PMS_ERR_INVALID_ARG,
                            "a consistency map of a batch is an output plane of the same batch");
                 return false;
             }
+        const float *init[4] = {J.init_depth.data, J.init_normal[0].data, J.init_normal[1].data,
+                                J.init_normal[2].data};
+        if (init[0])
+            for (auto p : init)
+                if (std::binary_search(sorted.begin(), sorted.end(), p)) {
+                    *st = fail(ctx, PMS_ERR_INVALID_ARG,
+                               "an initial plane of a batch is an output plane of the same batch");
+                    return false;
+                }
+    }
     return true;
 }
 
@@ -1070,6 +1120,8 @@ pms_status pms_default_params(pms_params *out)
     out->geo_rel_depth = 0.01;
     out->geo_min_views = 0;
     out->seed = 0;
+    out->median_radius = 0;
+    out->median_rel = 0.05;
     return PMS_OK;
 }
 
@@ -1445,6 +1497,208 @@ pms_status pms_consistency(pms_context *ctx, int32_t width, int32_t height,
     for (int k = 0; k < 3; ++k) J.normal[k] = normal_io[k];
     J.cost = cost_io;
     return run_specs(ctx, specs, static_cast<hipStream_t>(stream));
+}
+
+pms_status pms_warp_planes(pms_context *ctx, int32_t width, int32_t height,
+                           const pms_pose *src_pose, pms_plane src_depth,
+                           const pms_plane src_normal[3], const pms_pose *dst_pose,
+                           const pms_params *params, pms_plane dst_depth,
+                           const pms_plane dst_normal[3], void *stream)
+{
+    if (!ctx) return PMS_ERR_INVALID_ARG;
+    ctx->last_error.clear();
+    pms_status st = PMS_OK;
+    if (height < 1 || width != 2 * height)
+        return fail(ctx, PMS_ERR_INVALID_ARG, "size must be W x H with W == 2H >= 2");
+    if (!src_pose || !dst_pose || !finite_pose(*src_pose) || !finite_pose(*dst_pose))
+        return fail(ctx, PMS_ERR_INVALID_ARG, "null or non-finite pose");
+    if (!check_params(ctx, params, width, height, 0, &st)) return st;
+    if (!check_outputs(ctx, width, src_depth, src_normal, src_depth, &st)) return st;
+    if (!check_outputs(ctx, width, dst_depth, dst_normal, dst_depth, &st)) return st;
+    const float *srcs[4] = {src_depth.data, src_normal[0].data, src_normal[1].data, src_normal[2].data};
+    const float *dsts[4] = {dst_depth.data, dst_normal[0].data, dst_normal[1].data, dst_normal[2].data};
+    for (auto a : srcs)
+        for (auto b : dsts)
+            if (a == b) return fail(ctx, PMS_ERR_INVALID_ARG, "source and destination planes overlap");
+    if ((st = set_device(ctx)) != PMS_OK) return st;
+    Tables T;
+    if ((st = get_tables(ctx, width, height, &T)) != PMS_OK) return st;
+    const long long npx = (long long)width * height;
+    if ((st = ensure_work(ctx, (size_t)npx * sizeof(unsigned long long))) != PMS_OK) return st;
+    pms::WarpArgs A;
+    std::memset(&A, 0, sizeof A);
+    A.W = width;
+    A.H = height;
+    A.r = (params->patch_size - 1) / 2;
+    const pms::ViewPoseD rel = relative_pose64(*src_pose, *dst_pose);
+    for (int k = 0; k < 9; ++k) A.R[k] = rel.R[k];
+    for (int k = 0; k < 3; ++k) A.t[k] = rel.t[k];
+    A.dmin = params->depth_min;
+    A.dmax = params->depth_max;
+    A.sd = src_depth.data;
+    A.sn0 = src_normal[0].data;
+    A.sn1 = src_normal[1].data;
+    A.sn2 = src_normal[2].data;
+    A.psd = src_depth.pitch_elems;
+    A.psn0 = src_normal[0].pitch_elems;
+    A.psn1 = src_normal[1].pitch_elems;
+    A.psn2 = src_normal[2].pitch_elems;
+    A.dd = dst_depth.data;
+    A.dn0 = dst_normal[0].data;
+    A.dn1 = dst_normal[1].data;
+    A.dn2 = dst_normal[2].data;
+    A.pdd = dst_depth.pitch_elems;
+    A.pdn0 = dst_normal[0].pitch_elems;
+    A.pdn1 = dst_normal[1].pitch_elems;
+    A.pdn2 = dst_normal[2].pitch_elems;
+    A.zbuf = static_cast<unsigned long long *>(ctx->work);
+    A.tab_row64 = T.row64;
+    A.tab_col64 = T.col64;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    dim3 grid((unsigned)blocks_of(npx));
+    {
+        LaunchTimer timer(ctx, KK_WARP, s);
+        hipLaunchKernelGGL(pms::k_warp_clear, grid, dim3(pms::BLOCK), 0, s, A);
+        hipLaunchKernelGGL(pms::k_warp_splat, grid, dim3(pms::BLOCK), 0, s, A);
+        hipLaunchKernelGGL(pms::k_warp_resolve, grid, dim3(pms::BLOCK), 0, s, A);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(ctx, e, "warp");
+    return PMS_OK;
+}
+
+pms_status pms_view_filter(pms_context *ctx, const double centre_a[3], const double centre_b[3],
+                           const double *points, int64_t n_points, double min_deg,
+                           double max_deg, uint64_t *counts_out, void *stream)
+{
+    if (!ctx) return PMS_ERR_INVALID_ARG;
+    ctx->last_error.clear();
+    if (!centre_a || !centre_b || !counts_out || n_points < 0 || (n_points > 0 && !points))
+        return fail(ctx, PMS_ERR_INVALID_ARG, "null centre, points or counts, or n_points < 0");
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(centre_a[k]) || !std::isfinite(centre_b[k]))
+            return fail(ctx, PMS_ERR_INVALID_ARG, "non-finite camera centre");
+    if (!(min_deg <= max_deg) || !std::isfinite(min_deg) || !std::isfinite(max_deg))
+        return fail(ctx, PMS_ERR_INVALID_ARG, "need finite min_deg <= max_deg");
+    pms_status st = set_device(ctx);
+    if (st != PMS_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    unsigned long long *counts = reinterpret_cast<unsigned long long *>(counts_out);
+    hipLaunchKernelGGL(pms::k_count_clear, dim3(1), dim3(64), 0, s, counts);
+    if (n_points > 0)
+        hipLaunchKernelGGL(pms::k_view_filter, dim3((unsigned)blocks_of(n_points)), dim3(pms::BLOCK), 0, s,
+                           centre_a[0], centre_a[1], centre_a[2], centre_b[0], centre_b[1], centre_b[2],
+                           points, (long long)n_points, min_deg, max_deg, counts);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(ctx, e, "view filter");
+    return PMS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Validates the maps of pms_fuse / pms_coverage and fills their part of
+// the arguments.
+pms_status fuse_args(pms_context *ctx, int W, int H, int n_maps, const pms_plane *depths,
+                     const pms_pose *poses, pms::FuseArgs &A)
+{
+    if (H < 1 || W != 2 * H) return fail(ctx, PMS_ERR_INVALID_ARG, "size must be W x H with W == 2H >= 2");
+    if (n_maps < 1 || n_maps > PMS_MAX_MAPS || !depths || !poses)
+        return fail(ctx, PMS_ERR_INVALID_ARG, "need 1 <= n_maps <= 8 maps and poses");
+    pms_status st = PMS_OK;
+    for (int m = 0; m < n_maps; ++m) {
+        if (!check_plane(ctx, depths[m], W, "depth map", &st)) return st;
+        if (!finite_pose(poses[m])) return fail(ctx, PMS_ERR_INVALID_ARG, "non-finite map pose");
+    }
+    if ((st = set_device(ctx)) != PMS_OK) return st;
+    Tables T;
+    if ((st = get_tables(ctx, W, H, &T)) != PMS_OK) return st;
+    std::memset(&A, 0, sizeof A);
+    A.W = W;
+    A.H = H;
+    A.n_maps = n_maps;
+    for (int m = 0; m < n_maps; ++m) {
+        A.depth[m] = depths[m].data;
+        A.pitch[m] = depths[m].pitch_elems;
+        for (int k = 0; k < 9; ++k) A.pose[m].R[k] = poses[m].R[k];
+        for (int k = 0; k < 3; ++k) A.pose[m].t[k] = poses[m].t[k];
+    }
+    A.tab_row64 = T.row64;
+    A.tab_col64 = T.col64;
+    return PMS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pms_status pms_fuse(pms_context *ctx, int32_t width, int32_t height, int32_t n_maps,
+                    const pms_plane *depths, const pms_pose *poses, double voxel,
+                    uint8_t *keep_out, uint64_t *n_kept_out, void *stream)
+{
+    if (!ctx) return PMS_ERR_INVALID_ARG;
+    ctx->last_error.clear();
+    if (!keep_out || !n_kept_out) return fail(ctx, PMS_ERR_INVALID_ARG, "null keep or count output");
+    if (!(voxel > 0.0) || !std::isfinite(voxel)) return fail(ctx, PMS_ERR_INVALID_ARG, "voxel must be > 0");
+    pms::FuseArgs A;
+    pms_status st = fuse_args(ctx, width, height, n_maps, depths, poses, A);
+    if (st != PMS_OK) return st;
+    const long long points = (long long)width * height * n_maps;
+    unsigned long long cap = 1024;
+    while (cap < 2ULL * (unsigned long long)points) cap <<= 1;
+    if ((st = ensure_work(ctx, (size_t)cap * 2 * sizeof(unsigned long long))) != PMS_OK) return st;
+    A.voxel = voxel;
+    A.keys = static_cast<unsigned long long *>(ctx->work);
+    A.vals = A.keys + cap;
+    A.mask = cap - 1;
+    A.keep = keep_out;
+    A.count = reinterpret_cast<unsigned long long *>(n_kept_out);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    {
+        LaunchTimer timer(ctx, KK_FUSE, s);
+        hipLaunchKernelGGL(pms::k_fuse_clear, dim3((unsigned)blocks_of((long long)cap)), dim3(pms::BLOCK), 0, s, A);
+        hipLaunchKernelGGL(pms::k_fuse_insert, dim3((unsigned)blocks_of(points)), dim3(pms::BLOCK), 0, s, A);
+        hipLaunchKernelGGL(pms::k_fuse_mark, dim3((unsigned)blocks_of(points)), dim3(pms::BLOCK), 0, s, A);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(ctx, e, "fuse");
+    return PMS_OK;
+}
+
+pms_status pms_coverage(pms_context *ctx, int32_t width, int32_t height, int32_t n_maps,
+                        const pms_plane *depths, const pms_pose *poses, const uint8_t *keep,
+                        const pms_pose *view_pose, int32_t out_width, int32_t out_height,
+                        uint8_t *cover_out, uint64_t *n_covered_out, void *stream)
+{
+    if (!ctx) return PMS_ERR_INVALID_ARG;
+    ctx->last_error.clear();
+    if (!cover_out || !n_covered_out || !view_pose || !finite_pose(*view_pose))
+        return fail(ctx, PMS_ERR_INVALID_ARG, "null output or bad view pose");
+    if (out_height < 1 || out_width != 2 * out_height)
+        return fail(ctx, PMS_ERR_INVALID_ARG, "panorama must be W x H with W == 2H");
+    pms::FuseArgs A;
+    pms_status st = fuse_args(ctx, width, height, n_maps, depths, poses, A);
+    if (st != PMS_OK) return st;
+    for (int k = 0; k < 9; ++k) A.view.R[k] = view_pose->R[k];
+    for (int k = 0; k < 3; ++k) A.view.t[k] = view_pose->t[k];
+    A.Wc = out_width;
+    A.Hc = out_height;
+    A.cover = cover_out;
+    A.keep_in = keep;
+    A.count = reinterpret_cast<unsigned long long *>(n_covered_out);
+    const long long points = (long long)width * height * n_maps;
+    const long long pix = (long long)out_width * out_height;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    {
+        LaunchTimer timer(ctx, KK_FUSE, s);
+        hipLaunchKernelGGL(pms::k_cover_clear, dim3((unsigned)blocks_of(pix)), dim3(pms::BLOCK), 0, s, A);
+        hipLaunchKernelGGL(pms::k_cover_mark, dim3((unsigned)blocks_of(points)), dim3(pms::BLOCK), 0, s, A);
+        hipLaunchKernelGGL(pms::k_cover_count, dim3((unsigned)blocks_of(pix)), dim3(pms::BLOCK), 0, s, A);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(ctx, e, "coverage");
+    return PMS_OK;
 }
 
 pms_status pms_philox_stream(pms_context *ctx, uint64_t key0, uint64_t key1, uint64_t ctr0,
@@ -1915,12 +2169,15 @@ pms_status pms_server_step(pms_server *S, void *stream, int32_t *active_out, int
         else still.push_back(J);
     }
     {
-        Items fin, geo;
+        Items fin, med, geo;
         for (ServerJob *J : finishing) {
-            fin.emplace_back(J->slot, (int)blocks_of((long long)J->spec.W * J->spec.H), 0, 0);
-            if (J->job.n_maps > 0) geo.emplace_back(J->slot, (int)blocks_of((long long)J->spec.W * J->spec.H), 0, 0);
+            const int blocks = (int)blocks_of((long long)J->spec.W * J->spec.H);
+            fin.emplace_back(J->slot, blocks, 0, 0);
+            if (J->params.median_radius > 0) med.emplace_back(J->slot, blocks, 0, 0);
+            if (J->job.n_maps > 0) geo.emplace_back(J->slot, blocks, 0, 0);
         }
         add_rec(P, KK_FINALIZE, 0, 0, none, fin);
+        add_rec(P, KK_MEDIAN, 0, 0, none, med);
         add_rec(P, KK_CONSISTENCY, 0, 0, none, geo);
     }
     if ((int)P.pads.size() > S->max_pads || (int)P.entries.size() > S->max_entries)

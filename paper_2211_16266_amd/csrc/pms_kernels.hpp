@@ -63,7 +63,7 @@ constexpr int BLOCK = 256;    // threads per workgroup (4 waves)
 // to avoid a couple of spill slots outside the sample loop; the larger
 // variants keep the compiler's choice.
 #define PMS_OCCUPANCY(SPL) __attribute__((amdgpu_waves_per_eu((SPL) <= 9 ? 4 : 1, 8)))
-// Re-laid-out neighbour image: H + 2 rows of 2W + 4 values;
+// Re-laid-out neighbour image: H + 2 rows of 2W + 4 (value, difference) pairs;
 // logical column x is stored at x + W/2 + 2, logical row y at y + 1.
 
 // dtype codes of the C ABI
@@ -89,7 +89,7 @@ struct SweepArgs {
     int W, H, r, stride, side, P;
     float inv_P;
     int n_views, top_k;
-    float k_float;
+    float inv_k;  // fl(1 / top_k)
     float var_floor;
     float dmin, dmax, inv_dmin, inv_dmax;
     float kx, cx, ky, cy;  // u = lam * kx + cx, v = phi * ky + cy
@@ -126,6 +126,11 @@ struct SweepArgs {
     float *out_cost;
     long long out_pitch;
     float *view_out[MAXV];
+    // initial planes (e.g. the previous keyframe's map carried over); null
+    // for a random initialisation everywhere
+    const float *init_depth;
+    const float *init_n0, *init_n1, *init_n2;
+    long long init_pitch;
 };
 
 template <int DT>
@@ -133,17 +138,17 @@ struct Storage;
 template <>
 struct Storage<DT_F32> {
     using ref_t = float;
-    using pad_t = float;
+    using pad_t = float2;
 };
 template <>
 struct Storage<DT_F16> {
     using ref_t = __half;
-    using pad_t = __half;
+    using pad_t = float2;
 };
 template <>
 struct Storage<DT_U8> {
     using ref_t = uint8_t;
-    using pad_t = float;  // 8-bit neighbours are widened (and scaled) once
+    using pad_t = float2;
 };
 
 // ---------------------------------------------------------------------------
@@ -197,21 +202,22 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, int b
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, bytes, 0x00020000);
 }
 
-// Two horizontally adjacent values of a re-laid-out image at a byte offset.
+// Re-laid-out neighbour images hold, per position, the value and its
+// difference to the next column, (I(x), I(x+1) - I(x)) as float2, so that a
+// horizontal blend is one FMA. Bilinear sample from the pair of the row at
+// byte offset `off` and of the row below (au, av: fractions along x, y).
 template <typename P>
-__device__ __forceinline__ float2 load_pair(__amdgpu_buffer_rsrc_t r, int byte_off);
+__device__ __forceinline__ float bilinear(__amdgpu_buffer_rsrc_t r, int off, int rowb, float au, float av);
 
 template <>
-__device__ __forceinline__ float2 load_pair<float>(__amdgpu_buffer_rsrc_t r, int byte_off)
+__device__ __forceinline__ float bilinear<float2>(__amdgpu_buffer_rsrc_t r, int off, int rowb, float au,
+                                                  float av)
 {
-    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0));
-}
-
-template <>
-__device__ __forceinline__ float2 load_pair<__half>(__amdgpu_buffer_rsrc_t r, int byte_off)
-{
-    const __half2 h = __builtin_bit_cast(__half2, __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
-    return __half22float2(h);
+    const float2 p0 = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    const float2 p1 = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off + rowb, 0, 0));
+    const float top = fmaf(au, p0.y, p0.x);
+    const float bot = fmaf(au, p1.y, p1.x);
+    return fmaf(av, bot - top, top);
 }
 
 __device__ __forceinline__ void bearing(const SweepArgs &A, int x, int y, float b[3])
@@ -220,6 +226,14 @@ __device__ __forceinline__ void bearing(const SweepArgs &A, int x, int y, float 
     b[0] = rw.y * cl.x;
     b[1] = -rw.x;
     b[2] = rw.y * cl.y;
+}
+
+// floor(x) as an integer in one instruction (x finite and in int range).
+__device__ __forceinline__ int floor_int(float x)
+{
+    int r;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
 }
 
 // atan(t) for |t| <= tan(pi/8): t + t s P(s), s = t^2, with a degree-3 P
@@ -344,6 +358,125 @@ __device__ __forceinline__ void patch_setup(const SweepArgs &A, int x, int y, in
     }
 }
 
+// Everything a (pixel, hypothesis, view) shares between its samples.
+struct ViewSetup {
+    float h[9];          // homography turned by -lam0, on bearing offsets
+    float y0c, y2c;      // turned warped centre ray, x and z
+    float hzc;           // its horizontal length
+    float sdc, cdc;      // sin / cos of (centre latitude - phi0), scaled
+    float sp0, cp0;      // sin / cos of the anchor latitude phi0
+    int U0p, V0p;        // anchor pixel in re-laid-out storage
+    int short_ok;        // every sample angle is in the short atan range
+};
+
+// Sets up view j for plane (n, c) at the pixel of `pt`; mc = -c.
+template <int SPL>
+__device__ __forceinline__ void view_setup(const SweepArgs &A, const Patch<SPL> &pt, int j, double mc,
+                                           double nbp, float n0, float n1, float n2, ViewSetup &o)
+{
+    const ViewPoseD &V = A.pose[j];
+    const ViewPoseF &Vf = A.posef[j];
+    // warped centre ray in FP64: M b_p = (-c) R b_p - t (n . b_p), where
+    // M = (-c) R - t n^T is a positive multiple of the plane homography
+    double yc[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double rb = fma(V.R[3 * a], pt.bp64[0], fma(V.R[3 * a + 1], pt.bp64[1], V.R[3 * a + 2] * pt.bp64[2]));
+        yc[a] = fma(mc, rb, -V.t[a] * nbp);
+    }
+    // anchor: the pixel nearest to the warped centre
+    const float lamc = atan2_full((float)yc[0], (float)yc[2]);
+    const float phic = atan2_full((float)-yc[1], __builtin_amdgcn_sqrtf((float)(yc[0] * yc[0] + yc[2] * yc[2])));
+    int U0 = (int)floorf(fmaf(lamc, A.kx, A.cx) + 0.5f);
+    U0 = U0 >= A.W ? U0 - A.W : (U0 < 0 ? U0 + A.W : U0);
+    int V0 = (int)floorf(fmaf(phic, A.ky, A.cy) + 0.5f);
+    V0 = V0 < 0 ? 0 : (V0 > A.H - 1 ? A.H - 1 : V0);
+    const double2 lam0 = A.tab_col64[U0];  // (sin, cos) of the anchor longitude
+    const double2 phi0 = A.tab_row64[V0];  // (sin, cos) of the anchor latitude
+    o.U0p = U0 + (A.W >> 1) + 2;
+    o.V0p = V0 + 1;
+    // centre turned about the vertical by -lam0 (FP64). Its longitude is
+    // within half a pixel of lam0, so yr2 > 0 and |yr0| << yr2, and the
+    // horizontal length is yr2 + yr0^2 / (2 yr2) to FP64 precision.
+    const double yr0 = fma(lam0.y, yc[0], -lam0.x * yc[2]);
+    const double yr2 = fma(lam0.x, yc[0], lam0.y * yc[2]);
+    o.y0c = (float)yr0;
+    o.y2c = (float)yr2;
+    const double hzc = yr2 + (double)(0.5f * o.y0c * o.y0c / o.y2c);
+    // centre: sin and cos of (latitude - phi0), scaled by the ray length
+    o.sdc = (float)fma(-yc[1], phi0.y, -hzc * phi0.x);
+    o.cdc = (float)fma(hzc, phi0.y, -yc[1] * phi0.x);
+    o.hzc = (float)hzc;
+    o.sp0 = (float)phi0.x;
+    o.cp0 = (float)phi0.y;
+    const float sl0 = (float)lam0.x, cl0 = (float)lam0.y;
+    // the homography turned by -lam0, in FP32: it only maps the small
+    // offsets of the sample bearings from the centre bearing
+    const float mcf = (float)mc;
+    float mf2 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const float nk = k == 0 ? n0 : k == 1 ? n1 : n2;
+        const float m0 = fmaf(mcf, Vf.R[k], -Vf.t[0] * nk);
+        const float m1 = fmaf(mcf, Vf.R[3 + k], -Vf.t[1] * nk);
+        const float m2 = fmaf(mcf, Vf.R[6 + k], -Vf.t[2] * nk);
+        o.h[k] = fmaf(cl0, m0, -sl0 * m2);
+        o.h[3 + k] = m1;
+        o.h[6 + k] = fmaf(sl0, m0, cl0 * m2);
+        mf2 = fmaf(m0, m0, fmaf(m1, m1, fmaf(m2, m2, mf2)));
+    }
+    // Every sample offset e = h (b_q - b_p) satisfies |e| <= |M|_F dmax
+    // (turning keeps the norm). If the centre and that bound keep both
+    // angles of every sample in the short form's range, the short form
+    // equals the general one bit for bit.
+    const float E = __builtin_amdgcn_sqrtf(mf2) * A.patch_chord;
+    const float lon_den = o.y2c - E, lat_den = o.cdc - E;
+    o.short_ok = lon_den > 1e-30f && fabsf(o.y0c) + E <= SHORT_RANGE * lon_den && lat_den > 1e-30f &&
+                 fabsf(o.sdc) + E <= SHORT_RANGE * lat_den;
+}
+
+// Per-lane staging of view set-ups in LDS, one array per field (a lane's
+// slot is its thread index), so that every lane of a pixel can read the
+// set-up another lane of the same pixel prepared. Only lanes of one wave
+// exchange data, and a wave's LDS operations complete in order.
+constexpr int SETUP_WORDS = 19;
+
+struct SetupLds {
+    float w[SETUP_WORDS][BLOCK];
+};
+
+__device__ __forceinline__ void put_setup(SetupLds &L, int slot, const ViewSetup &v)
+{
+#pragma unroll
+    for (int k = 0; k < 9; ++k) L.w[k][slot] = v.h[k];
+    L.w[9][slot] = v.y0c;
+    L.w[10][slot] = v.y2c;
+    L.w[11][slot] = v.hzc;
+    L.w[12][slot] = v.sdc;
+    L.w[13][slot] = v.cdc;
+    L.w[14][slot] = v.sp0;
+    L.w[15][slot] = v.cp0;
+    L.w[16][slot] = __int_as_float(v.U0p);
+    L.w[17][slot] = __int_as_float(v.V0p);
+    L.w[18][slot] = __int_as_float(v.short_ok);
+}
+
+__device__ __forceinline__ void get_setup(const SetupLds &L, int slot, ViewSetup &v)
+{
+#pragma unroll
+    for (int k = 0; k < 9; ++k) v.h[k] = L.w[k][slot];
+    v.y0c = L.w[9][slot];
+    v.y2c = L.w[10][slot];
+    v.hzc = L.w[11][slot];
+    v.sdc = L.w[12][slot];
+    v.cdc = L.w[13][slot];
+    v.sp0 = L.w[14][slot];
+    v.cp0 = L.w[15][slot];
+    v.U0p = __float_as_int(L.w[16][slot]);
+    v.V0p = __float_as_int(L.w[17][slot]);
+    v.short_ok = __float_as_int(L.w[18][slot]);
+}
+
 // Aggregated cost of plane (d, n) at the pixel of `pt`: per view, warp every
 // sample, bilinear-sample the neighbour, two-pass NCC, cost = 1 - NCC or 2
 // when invalid; then the mean of the top_k smallest view costs. All lanes of
@@ -351,12 +484,17 @@ __device__ __forceinline__ void patch_setup(const SweepArgs &A, int x, int y, in
 // a multiple of LPP), so no slot is masked. When VIEWS is set, the pixel's
 // first lane writes each view's cost to A.view_out[j][out_index].
 //
+// Views are taken LPP at a time: lane l of the pixel prepares the set-up of
+// view jb + l (the FP64 centre ray, the anchor, the turned homography) and
+// stages it in LDS; every lane then reads each view's set-up from the slot
+// of the lane that made it.
+//
 // `bound`: the caller only uses the result if it is below `bound`. Once the
 // views still to come are fewer than top_k, the aggregate is at least the
 // same ascending sum with those views at cost 0; when that is already
 // >= bound the remaining views are skipped and a value >= bound returned.
-// Float addition and division round monotonically, so every decision the
-// caller takes is the one the full evaluation gives.
+// Float addition and multiplication by fl(1/top_k) round monotonically, so
+// every decision the caller takes is the one the full evaluation gives.
 template <typename PT, int LPP, int SPL, bool FULL, bool VIEWS>
 __device__ __forceinline__ float evaluate(const SweepArgs &A, const Patch<SPL> &pt, float d,
                                           float n0, float n1, float n2, int lane,
@@ -387,181 +525,146 @@ __device__ __forceinline__ float evaluate(const SweepArgs &A, const Patch<SPL> &
 #pragma unroll
     for (int i = 0; i < MAXV; ++i) top[i] = 0x40400000u;  // 3.0f
 
-    for (int j = 0; j < A.n_views; ++j) {
-        const ViewPoseD &V = A.pose[j];
-        const ViewPoseF &Vf = A.posef[j];
-        const __amdgpu_buffer_rsrc_t img = make_rsrc(A.pad[j], A.pad_bytes);
-        // warped centre ray in FP64: M b_p = (-c) R b_p - t (n . b_p), where
-        // M = (-c) R - t n^T is a positive multiple of the plane homography
-        double yc[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const double rb = fma(V.R[3 * a], pt.bp64[0], fma(V.R[3 * a + 1], pt.bp64[1], V.R[3 * a + 2] * pt.bp64[2]));
-            yc[a] = fma(mc, rb, -V.t[a] * nbp);
+    __shared__ SetupLds setup_lds;
+    const int slot0 = (int)threadIdx.x - lane;  // slot of the pixel's first lane
+    for (int jb = 0; jb < A.n_views; jb += LPP) {
+        if (jb + lane < A.n_views) {
+            ViewSetup mine;
+            view_setup<SPL>(A, pt, jb + lane, mc, nbp, n0, n1, n2, mine);
+            put_setup(setup_lds, threadIdx.x, mine);
         }
-        // anchor: the pixel nearest to the warped centre
-        const float lamc = atan2_full((float)yc[0], (float)yc[2]);
-        const float phic = atan2_full((float)-yc[1], __builtin_amdgcn_sqrtf((float)(yc[0] * yc[0] + yc[2] * yc[2])));
-        int U0 = (int)floorf(fmaf(lamc, A.kx, A.cx) + 0.5f);
-        U0 = U0 >= A.W ? U0 - A.W : (U0 < 0 ? U0 + A.W : U0);
-        int V0 = (int)floorf(fmaf(phic, A.ky, A.cy) + 0.5f);
-        V0 = V0 < 0 ? 0 : (V0 > A.H - 1 ? A.H - 1 : V0);
-        const double2 lam0 = A.tab_col64[U0];  // (sin, cos) of the anchor longitude
-        const double2 phi0 = A.tab_row64[V0];  // (sin, cos) of the anchor latitude
-        const int U0p = U0 + (A.W >> 1) + 2;   // anchor in re-laid-out storage
-        const int V0p = V0 + 1;
-        // centre turned about the vertical by -lam0 (FP64). Its longitude is
-        // within half a pixel of lam0, so yr2 > 0 and |yr0| << yr2, and the
-        // horizontal length is yr2 + yr0^2 / (2 yr2) to FP64 precision.
-        const double yr0 = fma(lam0.y, yc[0], -lam0.x * yc[2]);
-        const double yr2 = fma(lam0.x, yc[0], lam0.y * yc[2]);
-        const float y0c = (float)yr0, y2c = (float)yr2;
-        const double hzc = yr2 + (double)(0.5f * y0c * y0c / y2c);
-        // centre: sin and cos of (latitude - phi0), scaled by the ray length
-        const float sdc = (float)fma(-yc[1], phi0.y, -hzc * phi0.x);
-        const float cdc = (float)fma(hzc, phi0.y, -yc[1] * phi0.x);
-        const float hzcf = (float)hzc;
-        const float sp0 = (float)phi0.x, cp0 = (float)phi0.y;
-        const float sl0 = (float)lam0.x, cl0 = (float)lam0.y;
-        // the homography turned by -lam0, in FP32: it only maps the small
-        // offsets of the sample bearings from the centre bearing
-        const float mcf = (float)mc;
-        float h[9];
-        float mf2 = 0.0f;
+        __builtin_amdgcn_wave_barrier();
+        const int nr = min(LPP, A.n_views - jb);
+        for (int t = 0; t < nr; ++t) {
+            const int j = jb + t;
+            ViewSetup V;
+            get_setup(setup_lds, slot0 + t, V);
+            const __amdgpu_buffer_rsrc_t img = make_rsrc(A.pad[j], A.pad_bytes);
+            const float y0c = V.y0c, y2c = V.y2c, hzcf = V.hzc, sdc = V.sdc, cdc = V.cdc;
+            const float sp0 = V.sp0, cp0 = V.cp0;
+            const int U0p = V.U0p, V0p = V.V0p;
+            float s[SPL];
+            float sum = 0.0f;
+            // (the short form is compiled in for up to 9 samples per lane
+            // only: the larger variants cannot hold both copies at their
+            // occupancy)
+            if (SPL <= 9 && __all(V.short_ok)) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const float m0 = fmaf(mcf, Vf.R[k], -Vf.t[0] * (k == 0 ? n0 : k == 1 ? n1 : n2));
-            const float m1 = fmaf(mcf, Vf.R[3 + k], -Vf.t[1] * (k == 0 ? n0 : k == 1 ? n1 : n2));
-            const float m2 = fmaf(mcf, Vf.R[6 + k], -Vf.t[2] * (k == 0 ? n0 : k == 1 ? n1 : n2));
-            h[k] = fmaf(cl0, m0, -sl0 * m2);
-            h[3 + k] = m1;
-            h[6 + k] = fmaf(sl0, m0, cl0 * m2);
-            mf2 = fmaf(m0, m0, fmaf(m1, m1, fmaf(m2, m2, mf2)));
-        }
-        float s[SPL];
-        float sum = 0.0f;
-        // Every sample offset e = h (b_q - b_p) satisfies |e| <= |M|_F dmax
-        // (turning keeps the norm). If the centre and that bound keep both
-        // angles of every sample in the short form's range, the wave takes
-        // the short form, which then equals the general one bit for bit.
-        const float E = __builtin_amdgcn_sqrtf(mf2) * A.patch_chord;
-        const float lon_den = y2c - E, lat_den = cdc - E;
-        const bool short_ok = lon_den > 1e-30f && fabsf(y0c) + E <= SHORT_RANGE * lon_den &&
-                              lat_den > 1e-30f && fabsf(sdc) + E <= SHORT_RANGE * lat_den;
-        // (compiled in for up to 9 samples per lane only: the larger variants
-        // cannot hold both copies at their occupancy)
-        if (SPL <= 9 && __all(short_ok)) {
-    #pragma unroll
+                for (int i = 0; i < SPL; ++i) {
+                    const float bx = pt.b[i][0], by = pt.b[i][1], bz = pt.b[i][2];
+                    // the turned homography on the offset from the centre bearing
+                    const float e0 = fmaf(V.h[0], bx, fmaf(V.h[1], by, V.h[2] * bz));
+                    const float e1 = fmaf(V.h[3], bx, fmaf(V.h[4], by, V.h[5] * bz));
+                    const float e2 = fmaf(V.h[6], bx, fmaf(V.h[7], by, V.h[8] * bz));
+                    const float y0 = y0c + e0, y2 = y2c + e2;
+                    const float hz = __builtin_amdgcn_sqrtf(fmaf(y0, y0, y2 * y2));
+                    // hz - hzc without cancellation
+                    const float dhz = fmaf(e0, y0 + y0c, e2 * (y2 + y2c)) * __builtin_amdgcn_rcpf(hz + hzcf);
+                    const float sd = fmaf(-dhz, sp0, fmaf(-e1, cp0, sdc));
+                    const float cd = fmaf(dhz, cp0, fmaf(-e1, sp0, cdc));
+                    // longitude - lam0 and latitude - phi0
+                    const float dl = atan_core(y0 * __builtin_amdgcn_rcpf(y2));
+                    const float dp = atan_core(sd * __builtin_amdgcn_rcpf(cd));
+                    const float ul = dl * A.kx, vl = dp * A.ky;
+                    // whole and fractional pixel offsets from the anchor
+                    const float au = __builtin_amdgcn_fractf(ul), av = __builtin_amdgcn_fractf(vl);
+                    // |ul| <= W/2 keeps the column inside the repeated storage;
+                    // the latitude stays within the poles, so this clamp only
+                    // guards against rounding
+                    const int xi = U0p + floor_int(ul);
+                    const int yi = min(max(V0p + floor_int(vl), 0), A.H);
+                    const int off = (int)(__umul24((unsigned)yi, (unsigned)A.Wp) + (unsigned)xi) * (int)sizeof(PT);
+                    s[i] = bilinear<PT>(img, off, rowb, au, av);
+                    sum += FULL ? s[i] : s[i] * pt.wt[i];
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < SPL; ++i) {
+                    const float bx = pt.b[i][0], by = pt.b[i][1], bz = pt.b[i][2];
+                    const float e0 = fmaf(V.h[0], bx, fmaf(V.h[1], by, V.h[2] * bz));
+                    const float e1 = fmaf(V.h[3], bx, fmaf(V.h[4], by, V.h[5] * bz));
+                    const float e2 = fmaf(V.h[6], bx, fmaf(V.h[7], by, V.h[8] * bz));
+                    const float y0 = y0c + e0, y2 = y2c + e2;
+                    const float hz = __builtin_amdgcn_sqrtf(fmaf(y0, y0, y2 * y2));
+                    const float dhz = fmaf(e0, y0 + y0c, e2 * (y2 + y2c)) * __builtin_amdgcn_rcpf(hz + hzcf);
+                    const float sd = fmaf(-dhz, sp0, fmaf(-e1, cp0, sdc));
+                    const float cd = fmaf(dhz, cp0, fmaf(-e1, sp0, cdc));
+                    const float dl = atan2_full(y0, y2);
+                    const float dp = atan2_full(sd, cd);
+                    const float ul = dl * A.kx, vl = dp * A.ky;
+                    const float au = __builtin_amdgcn_fractf(ul), av = __builtin_amdgcn_fractf(vl);
+                    const int xi = U0p + floor_int(ul);
+                    const int yi = min(max(V0p + floor_int(vl), 0), A.H);
+                    const int off = (int)(__umul24((unsigned)yi, (unsigned)A.Wp) + (unsigned)xi) * (int)sizeof(PT);
+                    s[i] = bilinear<PT>(img, off, rowb, au, av);
+                    sum += FULL ? s[i] : s[i] * pt.wt[i];
+                }
+            }
+            sum = group_sum<LPP>(sum);
+            const float ms = sum * A.inv_P;
+            float m2 = 0.0f, cv = 0.0f;
+#pragma unroll
             for (int i = 0; i < SPL; ++i) {
-                const float bx = pt.b[i][0], by = pt.b[i][1], bz = pt.b[i][2];
-                // the turned homography on the offset from the centre bearing
-                const float e0 = fmaf(h[0], bx, fmaf(h[1], by, h[2] * bz));
-                const float e1 = fmaf(h[3], bx, fmaf(h[4], by, h[5] * bz));
-                const float e2 = fmaf(h[6], bx, fmaf(h[7], by, h[8] * bz));
-                const float y0 = y0c + e0, y2 = y2c + e2;
-                const float hz = __builtin_amdgcn_sqrtf(fmaf(y0, y0, y2 * y2));
-                // hz - hzc without cancellation
-                const float dhz = fmaf(e0, y0 + y0c, e2 * (y2 + y2c)) * __builtin_amdgcn_rcpf(hz + hzcf);
-                const float sd = fmaf(-dhz, sp0, fmaf(-e1, cp0, sdc));
-                const float cd = fmaf(dhz, cp0, fmaf(-e1, sp0, cdc));
-                // longitude - lam0 and latitude - phi0
-                const float dl = atan_core(y0 * __builtin_amdgcn_rcpf(y2));
-                const float dp = atan_core(sd * __builtin_amdgcn_rcpf(cd));
-                const float ul = dl * A.kx, vl = dp * A.ky;
-                const float fu = floorf(ul), fv = floorf(vl);
-                const float au = ul - fu, av = vl - fv;
-                // |ul| <= W/2 keeps the column inside the repeated storage; the
-                // latitude stays within the poles, so this clamp only guards
-                // against rounding
-                const int xi = U0p + (int)fu;
-                const int yi = min(max(V0p + (int)fv, 0), A.H);
-                const int off = (int)(__umul24((unsigned)yi, (unsigned)A.Wp) + (unsigned)xi) * (int)sizeof(PT);
-                const float2 p0 = load_pair<PT>(img, off);
-                const float2 p1 = load_pair<PT>(img, off + rowb);
-                const float top_r = fmaf(au, p0.y - p0.x, p0.x);
-                const float bot_r = fmaf(au, p1.y - p1.x, p1.x);
-                s[i] = fmaf(av, bot_r - top_r, top_r);
-                sum += FULL ? s[i] : s[i] * pt.wt[i];
+                const float e = FULL ? s[i] - ms : (s[i] - ms) * pt.wt[i];
+                m2 = fmaf(e, e, m2);
+                cv = fmaf(pt.rc[i], e, cv);
             }
-        } else {
-    #pragma unroll
-            for (int i = 0; i < SPL; ++i) {
-                const float bx = pt.b[i][0], by = pt.b[i][1], bz = pt.b[i][2];
-                // the turned homography on the offset from the centre bearing
-                const float e0 = fmaf(h[0], bx, fmaf(h[1], by, h[2] * bz));
-                const float e1 = fmaf(h[3], bx, fmaf(h[4], by, h[5] * bz));
-                const float e2 = fmaf(h[6], bx, fmaf(h[7], by, h[8] * bz));
-                const float y0 = y0c + e0, y2 = y2c + e2;
-                const float hz = __builtin_amdgcn_sqrtf(fmaf(y0, y0, y2 * y2));
-                // hz - hzc without cancellation
-                const float dhz = fmaf(e0, y0 + y0c, e2 * (y2 + y2c)) * __builtin_amdgcn_rcpf(hz + hzcf);
-                const float sd = fmaf(-dhz, sp0, fmaf(-e1, cp0, sdc));
-                const float cd = fmaf(dhz, cp0, fmaf(-e1, sp0, cdc));
-                // longitude - lam0 and latitude - phi0
-                const float dl = atan2_full(y0, y2);
-                const float dp = atan2_full(sd, cd);
-                const float ul = dl * A.kx, vl = dp * A.ky;
-                const float fu = floorf(ul), fv = floorf(vl);
-                const float au = ul - fu, av = vl - fv;
-                // |ul| <= W/2 keeps the column inside the repeated storage; the
-                // latitude stays within the poles, so this clamp only guards
-                // against rounding
-                const int xi = U0p + (int)fu;
-                const int yi = min(max(V0p + (int)fv, 0), A.H);
-                const int off = (int)(__umul24((unsigned)yi, (unsigned)A.Wp) + (unsigned)xi) * (int)sizeof(PT);
-                const float2 p0 = load_pair<PT>(img, off);
-                const float2 p1 = load_pair<PT>(img, off + rowb);
-                const float top_r = fmaf(au, p0.y - p0.x, p0.x);
-                const float bot_r = fmaf(au, p1.y - p1.x, p1.x);
-                s[i] = fmaf(av, bot_r - top_r, top_r);
-                sum += FULL ? s[i] : s[i] * pt.wt[i];
+            m2 = group_sum<LPP>(m2);
+            cv = group_sum<LPP>(cv);
+            const float vs = m2 * A.inv_P, cov = cv * A.inv_P;
+            float cj;
+            if (pt.var_r < A.var_floor || vs < A.var_floor) {
+                cj = 2.0f;
+            } else {
+                float ncc = cov * __builtin_amdgcn_rsqf(pt.var_r * vs);
+                ncc = fminf(fmaxf(ncc, -1.0f), 1.0f);
+                cj = 1.0f - ncc;
             }
-        }
-        sum = group_sum<LPP>(sum);
-        const float ms = sum * A.inv_P;
-        float m2 = 0.0f, cv = 0.0f;
+            if (VIEWS && lane == 0) A.view_out[j][out_index] = cj;
+            // the next round overwrites the slots read above
+            __builtin_amdgcn_wave_barrier();
+            // insertion into the ascending list of the smallest costs so
+            // far; slots past top_k only collect larger costs and are never
+            // summed, so the list is kept 4 long whenever top_k <= 4 (a
+            // wave-uniform choice)
+            unsigned cb = __float_as_uint(cj);
+            if (A.top_k <= 4) {
 #pragma unroll
-        for (int i = 0; i < SPL; ++i) {
-            const float e = FULL ? s[i] - ms : (s[i] - ms) * pt.wt[i];
-            m2 = fmaf(e, e, m2);
-            cv = fmaf(pt.rc[i], e, cv);
-        }
-        m2 = group_sum<LPP>(m2);
-        cv = group_sum<LPP>(cv);
-        const float vs = m2 * A.inv_P, cov = cv * A.inv_P;
-        float cj;
-        if (pt.var_r < A.var_floor || vs < A.var_floor) {
-            cj = 2.0f;
-        } else {
-            float ncc = cov * __builtin_amdgcn_rsqf(pt.var_r * vs);
-            ncc = fminf(fmaxf(ncc, -1.0f), 1.0f);
-            cj = 1.0f - ncc;
-        }
-        if (VIEWS && lane == 0) A.view_out[j][out_index] = cj;
-        unsigned cb = __float_as_uint(cj);
+                for (int i = 0; i < 4; ++i) {
+                    const unsigned lo = min(top[i], cb), hi = max(top[i], cb);
+                    top[i] = lo;
+                    cb = hi;
+                }
+            } else {
 #pragma unroll
-        for (int i = 0; i < MAXV; ++i)
-            if (i < A.top_k) {
-                const unsigned lo = min(top[i], cb), hi = max(top[i], cb);
-                top[i] = lo;
-                cb = hi;
+                for (int i = 0; i < MAXV; ++i) {
+                    const unsigned lo = min(top[i], cb), hi = max(top[i], cb);
+                    top[i] = lo;
+                    cb = hi;
+                }
             }
-        if (!VIEWS) {
-            const int have = A.top_k - (A.n_views - 1 - j);  // evaluated costs in the bound
-            if (have > 0) {
-                float lb = 0.0f;
+            if (!VIEWS) {
+                const int have = A.top_k - (A.n_views - 1 - j);  // evaluated costs in the bound
+                if (have > 0) {
+                    float lb = 0.0f;
 #pragma unroll
-                for (int i = 0; i < MAXV; ++i)
-                    if (i < have) lb += __uint_as_float(top[i]);
-                if (lb / A.k_float >= bound) return lb / A.k_float;
+                    for (int i = 0; i < MAXV; ++i) {
+                        if (i >= have) break;
+                        lb += __uint_as_float(top[i]);
+                    }
+                    if (lb * A.inv_k >= bound) return lb * A.inv_k;
+                }
             }
         }
     }
+    // the mean as sum x fl(1/k): monotone in the sum like the bound above
     float acc = 0.0f;
 #pragma unroll
-    for (int i = 0; i < MAXV; ++i)
-        if (i < A.top_k) acc += __uint_as_float(top[i]);
-    return acc / A.k_float;
+    for (int i = 0; i < MAXV; ++i) {
+        if (i >= A.top_k) break;
+        acc += __uint_as_float(top[i]);
+    }
+    return acc * A.inv_k;
 }
 
 // ---------------------------------------------------------------------------
@@ -575,6 +678,8 @@ struct IoArgs {
     float *cost;
     float *depth, *n0, *n1, *n2, *cplane;
     long long pd, pn0, pn1, pn2, pc;  // pitches in elements
+    int median_radius;                // median post-filter (0 = off)
+    double median_rel;
 };
 
 // Geometric consistency of one keyframe against up to MAXV depth maps.
@@ -604,19 +709,21 @@ struct PadJob {
     void *dst;
 };
 
-// A launch covers a list of entries; entry e owns the logical blocks
-// [first_e, first_{e+1}) (the list ends with a sentinel holding the total)
-// and names its job and, for a half-sweep, the job's iteration and colour.
-// Jobs at different stages of their sweep can share one launch.
+// A launch covers a list of entries. Entry e has `tiles` tiles (or blocks),
+// split into 8 runs of per_xcd = ceil(tiles / 8), one per XCD; on every XCD
+// it owns the workgroup slots [first_e, first_{e+1}) (the list ends with a
+// sentinel whose `first` is the slot count). It names its job and, for a
+// half-sweep, the job's iteration and colour, so jobs at different stages
+// of their sweep can share one launch.
 struct Entry {
-    int job, first, iteration, colour;
+    int job, first, tiles, per_xcd, iteration, colour;
 };
 
 struct Launch {
     const void *table;      // JobArgs[] or PadJob[]
     const Entry *entries;   // n_entries + 1 entries
     int n_entries;
-    int per_xcd;            // logical blocks per XCD; the grid is 8 * per_xcd
+    int slots;              // workgroup slots per XCD; the grid is 8 * slots
 };
 
 // The tables are written before a launch and only read by it: reading them
@@ -631,25 +738,27 @@ __device__ __forceinline__ const T *const_view(const void *base, int i)
     return (const T *)(p + i);
 }
 
-// Logical block of this workgroup: the 8 XCDs receive workgroups round
-// robin, and logical block t = xcd * per_xcd + slot gives each XCD a
-// contiguous run of tiles (rows of one job), whose neighbour image rows then
-// stay in that XCD's L2. Returns false past the last entry.
+// Entry and tile of this workgroup. The 8 XCDs receive workgroups round
+// robin; slot = blockIdx / 8 on XCD x = blockIdx % 8 serves tile
+// x * per_xcd + (slot - first) of its entry, so every XCD walks one
+// contiguous band of rows of each job and keeps the matching rows of that
+// job's neighbour images in its own L2. Returns false for the few slots
+// past an entry's last tile.
 __device__ __forceinline__ bool block_entry(const Launch &L, int &e, int &local)
 {
     const int bid = blockIdx.x;
-    const int t = (bid & 7) * L.per_xcd + (bid >> 3);
+    const int slot = bid >> 3;
     const Entry *E = const_view<Entry>(L.entries, 0);
-    if (t >= E[L.n_entries].first) return false;
+    if (slot >= E[L.n_entries].first) return false;
     int lo = 0, hi = L.n_entries - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (E[mid].first <= t) lo = mid;
+        if (E[mid].first <= slot) lo = mid;
         else hi = mid - 1;
     }
     e = lo;
-    local = t - E[lo].first;
-    return true;
+    local = (bid & 7) * E[lo].per_xcd + (slot - E[lo].first);
+    return local < E[lo].tiles;
 }
 
 // Position of this thread's pixel inside its job's tile.
@@ -690,21 +799,20 @@ __global__ void k_tables(int W, int H, float2 *row, float2 *col, double2 *row64,
 
 // Re-lays out neighbour images: storage row py holds image row
 // clamp(py - 1, 0, H - 1), storage column px holds image column
-// (px - W/2 - 2) mod W. 16-bit images keep their values; the others are
-// widened to FP32 (8-bit ones scaled to [0, 1]).
-template <typename TS, typename TD>
+// c = (px - W/2 - 2) mod W as the pair (I(c), I(c + 1 mod W) - I(c)) in
+// FP32 (16-bit values widen exactly; 8-bit ones are scaled to [0, 1]).
+template <typename TS>
 __device__ __forceinline__ void pad_one(const PadJob &J, long long i)
 {
     const int py = (int)(i / J.Wp), px = (int)(i - (long long)py * J.Wp);
     int sx = px - (J.W >> 1) - 2;
     sx = sx < 0 ? sx + J.W : sx;
     sx = sx >= J.W ? sx - J.W : sx;
+    const int sx1 = sx + 1 == J.W ? 0 : sx + 1;
     const int sy = py == 0 ? 0 : (py > J.H ? J.H - 1 : py - 1);
-    if constexpr (std::is_same<TS, __half>::value)
-        static_cast<__half *>(J.dst)[i] =
-            reinterpret_cast<const __half *>(static_cast<const char *>(J.src.ptr) + (long long)sy * J.src.pitch)[sx];
-    else
-        static_cast<float *>(J.dst)[i] = load_px<TS>(J.src, sx, sy);
+    const float a = load_px<TS>(J.src, sx, sy);
+    const float b = load_px<TS>(J.src, sx1, sy);
+    static_cast<float2 *>(J.dst)[i] = make_float2(a, b - a);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_pad(Launch L)
@@ -715,9 +823,9 @@ __global__ __launch_bounds__(BLOCK) void k_pad(Launch L)
     const PadJob &J = *const_view<PadJob>(L.table, E.job);
     const long long i = (long long)local * BLOCK + threadIdx.x;
     if (i >= (long long)(J.H + 2) * J.Wp) return;
-    if (J.dtype == DT_F16) pad_one<__half, __half>(J, i);
-    else if (J.dtype == DT_U8) pad_one<uint8_t, float>(J, i);
-    else pad_one<float, float>(J, i);
+    if (J.dtype == DT_F16) pad_one<__half>(J, i);
+    else if (J.dtype == DT_U8) pad_one<uint8_t>(J, i);
+    else pad_one<float>(J, i);
 }
 
 // Reference patch mean and variance per valid pixel (two-pass, FP32).
@@ -760,8 +868,9 @@ __global__ __launch_bounds__(BLOCK) void k_refstats(Launch L)
     else refstats_one<float>(A, i);
 }
 
-// Random initialisation (Sec. III-B): depth uniform in inverse depth, normal
-// uniform on the sphere turned towards the camera, and its cost.
+// Initialisation (Sec. III-B): depth uniform in inverse depth, normal
+// uniform on the sphere turned towards the camera -- or the supplied plane
+// (plane-map warping) where it is usable -- and its cost.
 template <int DT, int LPP, int SPL, bool FULL>
 __device__ __forceinline__ void init_tile(const SweepArgs &A, int tile)
 {
@@ -785,7 +894,7 @@ __device__ __forceinline__ void init_tile(const SweepArgs &A, int tile)
     float u[4];
     uniforms(A.seed, (unsigned long long)idx, 0ULL, 0ULL, u);
     const float rho = fmaf(u[0], A.inv_dmin - A.inv_dmax, A.inv_dmax);
-    const float d = 1.0f / rho;
+    const float d_rand = 1.0f / rho;
     const float z = 2.0f * u[1] - 1.0f, a = 6.283185307179586f * u[2];
     const float s = sqrtf(fmaxf(0.0f, 1.0f - z * z));
     float sa, ca;
@@ -800,6 +909,21 @@ __device__ __forceinline__ void init_tile(const SweepArgs &A, int tile)
         n0 = -pt.bp[0];
         n1 = -pt.bp[1];
         n2 = -pt.bp[2];
+    }
+    float d = d_rand;
+    if (A.init_depth) {
+        // a supplied plane replaces the random one where it is usable: depth
+        // in range and the normal facing the camera (tested in FP64)
+        const long long pi = (long long)y * A.init_pitch + x;
+        const float di = A.init_depth[pi];
+        const float m0 = A.init_n0[pi], m1 = A.init_n1[pi], m2 = A.init_n2[pi];
+        const double mb = (double)m0 * pt.bp64[0] + (double)m1 * pt.bp64[1] + (double)m2 * pt.bp64[2];
+        if (di >= A.dmin && di <= A.dmax && mb < 0.0) {
+            d = di;
+            n0 = m0;
+            n1 = m1;
+            n2 = m2;
+        }
     }
     const float c = evaluate<PT, LPP, SPL, FULL, false>(A, pt, d, n0, n1, n2, lane, 0);
     if (lane == 0) {
@@ -831,6 +955,10 @@ __device__ __forceinline__ void halfsweep_tile(const SweepArgs &A, int tile, int
     float bd = cur.w, bn0 = cur.x, bn1 = cur.y, bn2 = cur.z;
     float bc = A.cost[idx];
 
+    // the previous propagation candidate (a repeat of it, or of the current
+    // plane, scores exactly the same cost again and cannot win under the
+    // strict rule, so it is not evaluated a second time)
+    float pd = -1.0f, pn0 = 0.0f, pn1 = 0.0f, pn2 = 0.0f;
     for (int o = 0; o < A.n_offsets; ++o) {
         int qx = x + A.off_x[o];
         qx = qx < 0 ? qx + A.W : (qx >= A.W ? qx - A.W : qx);
@@ -845,6 +973,15 @@ __device__ __forceinline__ void halfsweep_tile(const SweepArgs &A, int tile, int
         if (!(den < 0.0f)) continue;
         const float dd = cq / den;
         if (!(dd >= A.dmin && dd <= A.dmax)) continue;
+        const bool same_best = __float_as_uint(dd) == __float_as_uint(bd) && __float_as_uint(sq.x) == __float_as_uint(bn0) &&
+                               __float_as_uint(sq.y) == __float_as_uint(bn1) && __float_as_uint(sq.z) == __float_as_uint(bn2);
+        const bool same_prev = __float_as_uint(dd) == __float_as_uint(pd) && __float_as_uint(sq.x) == __float_as_uint(pn0) &&
+                               __float_as_uint(sq.y) == __float_as_uint(pn1) && __float_as_uint(sq.z) == __float_as_uint(pn2);
+        if (same_best || same_prev) continue;
+        pd = dd;
+        pn0 = sq.x;
+        pn1 = sq.y;
+        pn2 = sq.z;
         const float c = evaluate<PT, LPP, SPL, FULL, false>(A, pt, dd, sq.x, sq.y, sq.z, lane, 0, bc);
         if (c < bc) {
             bc = c;
@@ -956,6 +1093,69 @@ __global__ __launch_bounds__(BLOCK) void k_finalize(Launch L)
     finalize_one(A, i);
 }
 
+// Median post-filter (Sec. III-C, item 2): a valid depth (from the plane
+// state, i.e. before any removal) that deviates from the lower median of the
+// valid depths in its (2R+1)^2 window (longitude wrapping, rows beyond the
+// image left out) by more than median_rel times that median is removed from
+// the output planes. The k-th smallest of the window is found by bisection
+// on the bit pattern: positive floats order like their bits.
+__device__ __forceinline__ float state_depth(const IoArgs &A, int x, int y)
+{
+    if (y < A.r || y > A.H - 1 - A.r) return 0.0f;
+    const float d = A.state[(long long)y * A.W + x].w;
+    return d > 0.0f ? d : 0.0f;
+}
+
+__device__ __forceinline__ void median_one(const IoArgs &A, long long i)
+{
+    const int y = (int)(i / A.W), x = (int)(i - (long long)y * A.W);
+    const float d = state_depth(A, x, y);
+    if (!(d > 0.0f)) return;
+    const int R = A.median_radius;
+    const int y0 = max(y - R, 0), y1 = min(y + R, A.H - 1);
+    int n = 0;
+    for (int yy = y0; yy <= y1; ++yy)
+        for (int dx = -R; dx <= R; ++dx) {
+            int xx = x + dx;
+            xx = xx < 0 ? xx + A.W : (xx >= A.W ? xx - A.W : xx);
+            n += state_depth(A, xx, yy) > 0.0f ? 1 : 0;
+        }
+    const int k = (n - 1) / 2;
+    // smallest bit pattern b with #{v <= b} > k
+    unsigned lo = 1u, hi = 0x7f800000u;
+    while (lo < hi) {
+        const unsigned mid = lo + ((hi - lo) >> 1);
+        int c = 0;
+        for (int yy = y0; yy <= y1; ++yy)
+            for (int dx = -R; dx <= R; ++dx) {
+                int xx = x + dx;
+                xx = xx < 0 ? xx + A.W : (xx >= A.W ? xx - A.W : xx);
+                const float v = state_depth(A, xx, yy);
+                c += (v > 0.0f && __float_as_uint(v) <= mid) ? 1 : 0;
+            }
+        if (c > k) hi = mid;
+        else lo = mid + 1;
+    }
+    const double m = (double)__uint_as_float(lo);
+    if (fabs((double)d - m) > A.median_rel * m) {
+        A.depth[(long long)y * A.pd + x] = 0.0f;
+        A.n0[(long long)y * A.pn0 + x] = 0.0f;
+        A.n1[(long long)y * A.pn1 + x] = 0.0f;
+        A.n2[(long long)y * A.pn2 + x] = 0.0f;
+        A.cplane[(long long)y * A.pc + x] = 2.0f;
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_median(Launch L)
+{
+    int e, local;
+    if (!block_entry(L, e, local)) return;
+    const IoArgs &A = const_view<JobArgs>(L.table, const_view<Entry>(L.entries, e)->job)->io;
+    const long long i = (long long)local * BLOCK + threadIdx.x;
+    if (i >= (long long)A.W * A.H) return;
+    median_one(A, i);
+}
+
 // Plane state from caller planes (test hook).
 __global__ __launch_bounds__(BLOCK) void k_load_state(IoArgs A)
 {
@@ -1058,6 +1258,315 @@ __global__ __launch_bounds__(BLOCK) void k_consistency(Launch L)
     const long long i = (long long)local * BLOCK + threadIdx.x;
     if (i >= (long long)A.W * A.H) return;
     consistency_one(A, i);
+}
+
+// ---------------------------------------------------------------------------
+// plane-map warping (Sec. III-B): the previous keyframe's plane map carried
+// into the current keyframe
+// ---------------------------------------------------------------------------
+
+struct WarpArgs {
+    int W, H, r;
+    double R[9], t[3];  // source camera -> destination camera, FP64
+    double dmin, dmax;
+    const float *sd, *sn0, *sn1, *sn2;
+    long long psd, psn0, psn1, psn2;
+    float *dd, *dn0, *dn1, *dn2;
+    long long pdd, pdn0, pdn1, pdn2;
+    unsigned long long *zbuf;  // per destination pixel: (float range bits << 32) | source index
+    const double2 *tab_row64, *tab_col64;
+};
+
+__global__ __launch_bounds__(BLOCK) void k_warp_clear(WarpArgs A)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < (long long)A.W * A.H) A.zbuf[i] = ~0ULL;
+}
+
+__device__ __forceinline__ void warp_point(const WarpArgs &A, int x, int y, float d, double Y[3])
+{
+    const double2 rw = A.tab_row64[y], cl = A.tab_col64[x];
+    const double X0 = (double)d * (rw.y * cl.x), X1 = (double)d * -rw.x, X2 = (double)d * (rw.y * cl.y);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) Y[k] = A.R[3 * k] * X0 + A.R[3 * k + 1] * X1 + A.R[3 * k + 2] * X2 + A.t[k];
+}
+
+// Each valid source pixel claims the destination pixel nearest to the
+// projection of its plane point; the smallest key (nearest point, then the
+// lower source index) wins, so the outcome does not depend on the order of
+// the 64-bit atomics.
+__global__ __launch_bounds__(BLOCK) void k_warp_splat(WarpArgs A)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)A.W * A.H) return;
+    const int y = (int)(i / A.W), x = (int)(i - (long long)y * A.W);
+    if (y < A.r || y > A.H - 1 - A.r) return;
+    const float d = A.sd[(long long)y * A.psd + x];
+    if (!(d > 0.0f)) return;
+    double Y[3];
+    warp_point(A, x, y, d, Y);
+    const double range = sqrt(Y[0] * Y[0] + Y[1] * Y[1] + Y[2] * Y[2]);
+    if (!(range > 0.0)) return;
+    const double PI = 3.14159265358979323846;
+    const double lam = atan2(Y[0], Y[2]);
+    const double phi = atan2(-Y[1], hypot(Y[0], Y[2]));
+    const double u = A.W * (lam + PI) / (2.0 * PI) - 0.5;
+    const double v = A.H * (PI / 2.0 - phi) / PI - 0.5;
+    double fx = floor(u + 0.5);
+    fx -= A.W * floor(fx / A.W);
+    int xi = (int)fx;
+    xi = xi >= A.W ? xi - A.W : (xi < 0 ? xi + A.W : xi);
+    const double fy = floor(v + 0.5);
+    const int yi = fy < 0.0 ? 0 : (fy > A.H - 1 ? A.H - 1 : (int)fy);
+    if (yi < A.r || yi > A.H - 1 - A.r) return;
+    const unsigned long long key =
+        ((unsigned long long)__float_as_uint((float)range) << 32) | (unsigned long long)(unsigned)i;
+    atomicMin(&A.zbuf[(long long)yi * A.W + xi], key);
+}
+
+// The winning plane (normal R n through the moved point) re-intersected
+// with the destination pixel's ray; kept if it faces the camera and its
+// depth is in range.
+__global__ __launch_bounds__(BLOCK) void k_warp_resolve(WarpArgs A)
+{
+    const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= (long long)A.W * A.H) return;
+    const int yd = (int)(j / A.W), xd = (int)(j - (long long)yd * A.W);
+    const unsigned long long key = A.zbuf[j];
+    float od = 0.0f, o0 = 0.0f, o1 = 0.0f, o2 = 0.0f;
+    if (key != ~0ULL) {
+        const long long i = (long long)(key & 0xffffffffULL);
+        const int y = (int)(i / A.W), x = (int)(i - (long long)y * A.W);
+        const float d = A.sd[(long long)y * A.psd + x];
+        double Y[3];
+        warp_point(A, x, y, d, Y);
+        const double n0 = A.sn0[(long long)y * A.psn0 + x], n1 = A.sn1[(long long)y * A.psn1 + x],
+                     n2 = A.sn2[(long long)y * A.psn2 + x];
+        double nd[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) nd[k] = A.R[3 * k] * n0 + A.R[3 * k + 1] * n1 + A.R[3 * k + 2] * n2;
+        const double2 rw = A.tab_row64[yd], cl = A.tab_col64[xd];
+        const double b0 = rw.y * cl.x, b1 = -rw.x, b2 = rw.y * cl.y;
+        const double den = nd[0] * b0 + nd[1] * b1 + nd[2] * b2;
+        if (den < 0.0) {
+            const double dd = (nd[0] * Y[0] + nd[1] * Y[1] + nd[2] * Y[2]) / den;
+            if (dd >= A.dmin && dd <= A.dmax) {
+                od = (float)dd;
+                o0 = (float)nd[0];
+                o1 = (float)nd[1];
+                o2 = (float)nd[2];
+            }
+        }
+    }
+    A.dd[(long long)yd * A.pdd + xd] = od;
+    A.dn0[(long long)yd * A.pdn0 + xd] = o0;
+    A.dn1[(long long)yd * A.pdn1 + xd] = o1;
+    A.dn2[(long long)yd * A.pdn2 + xd] = o2;
+}
+
+// ---------------------------------------------------------------------------
+// view filter (Sec. III-A, Eq. 1)
+// ---------------------------------------------------------------------------
+
+__global__ void k_count_clear(unsigned long long *counts)
+{
+    if (threadIdx.x < 2) counts[threadIdx.x] = 0ULL;
+}
+
+// Per sparse point the angle between the directions to the two camera
+// centres (FP64); the wave adds its counts of points in [min_deg, max_deg]
+// and of points not at a centre with one atomic each.
+__global__ __launch_bounds__(BLOCK) void k_view_filter(double ax, double ay, double az, double bx,
+                                                       double by, double bz, const double *pts,
+                                                       long long n, double min_deg, double max_deg,
+                                                       unsigned long long *counts)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    bool counted = false, in_range = false;
+    if (i < n) {
+        const double px = pts[3 * i], py = pts[3 * i + 1], pz = pts[3 * i + 2];
+        const double a0 = ax - px, a1 = ay - py, a2 = az - pz;
+        const double b0 = bx - px, b1 = by - py, b2 = bz - pz;
+        const double la = sqrt(a0 * a0 + a1 * a1 + a2 * a2), lb = sqrt(b0 * b0 + b1 * b1 + b2 * b2);
+        if (la > 0.0 && lb > 0.0) {
+            double cs = (a0 * b0 + a1 * b1 + a2 * b2) / (la * lb);
+            cs = cs > 1.0 ? 1.0 : (cs < -1.0 ? -1.0 : cs);
+            const double deg = acos(cs) * (180.0 / 3.14159265358979323846);
+            counted = true;
+            in_range = deg >= min_deg && deg <= max_deg;
+        }
+    }
+    const unsigned long long cmask = __ballot(counted), rmask = __ballot(in_range);
+    if ((threadIdx.x & 63) == 0) {
+        if (rmask) atomicAdd(&counts[0], (unsigned long long)__popcll(rmask));
+        if (cmask) atomicAdd(&counts[1], (unsigned long long)__popcll(cmask));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// dense point-cloud fusion (Sec. III, point-cloud thread): voxel
+// de-duplication of the points of buffered depth maps, and the coverage of a
+// panorama by the kept points (the paper's completeness measure)
+// ---------------------------------------------------------------------------
+
+constexpr unsigned long long EMPTY_KEY = ~0ULL;
+
+struct FuseArgs {
+    int W, H, n_maps;
+    double voxel;
+    const float *depth[MAXV];
+    long long pitch[MAXV];
+    ViewPoseD pose[MAXV];  // world -> camera of each map
+    const double2 *tab_row64, *tab_col64;
+    unsigned long long *keys, *vals;  // hash table: voxel key, first (map, pixel)
+    unsigned long long mask;          // capacity - 1 (a power of two)
+    unsigned char *keep;              // n_maps x H x W
+    unsigned long long *count;
+    // coverage
+    ViewPoseD view;
+    int Wc, Hc;
+    unsigned char *cover;
+    const unsigned char *keep_in;     // null: every valid pixel
+};
+
+__device__ __forceinline__ bool fuse_point(const FuseArgs &A, int m, long long i, double X[3])
+{
+    const int y = (int)(i / A.W), x = (int)(i - (long long)y * A.W);
+    const float d = A.depth[m][(long long)y * A.pitch[m] + x];
+    if (!(d > 0.0f)) return false;
+    const double2 rw = A.tab_row64[y], cl = A.tab_col64[x];
+    const ViewPoseD &P = A.pose[m];
+    const double c0 = (double)d * (rw.y * cl.x) - P.t[0];
+    const double c1 = (double)d * -rw.x - P.t[1];
+    const double c2 = (double)d * (rw.y * cl.y) - P.t[2];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) X[k] = P.R[k] * c0 + P.R[3 + k] * c1 + P.R[6 + k] * c2;
+    return true;
+}
+
+// Voxel coordinates packed 21 bits each (offset 2^20); false beyond that.
+__device__ __forceinline__ bool voxel_key(const FuseArgs &A, const double X[3], unsigned long long &key)
+{
+    key = 0ULL;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double v = floor(X[k] / A.voxel);
+        if (!(v >= -1048576.0 && v < 1048576.0)) return false;
+        key = (key << 21) | (unsigned long long)((long long)v + 1048576LL);
+    }
+    return true;
+}
+
+__device__ __forceinline__ unsigned long long hash64(unsigned long long k)
+{
+    k ^= k >> 33;
+    k *= 0xff51afd7ed558ccdULL;
+    k ^= k >> 33;
+    k *= 0xc4ceb9fe1a85ec53ULL;
+    k ^= k >> 33;
+    return k;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_fuse_clear(FuseArgs A)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i <= (long long)A.mask) {
+        A.keys[i] = EMPTY_KEY;
+        A.vals[i] = EMPTY_KEY;
+    }
+    if (i == 0) A.count[0] = 0ULL;
+}
+
+// Each point claims its voxel's slot (linear probing; the table holds at
+// least twice as many slots as points, so a free slot is always found) and
+// lowers the slot's value to its (map, pixel) order.
+__global__ __launch_bounds__(BLOCK) void k_fuse_insert(FuseArgs A)
+{
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long HW = (long long)A.W * A.H;
+    if (g >= HW * A.n_maps) return;
+    const int m = (int)(g / HW);
+    double X[3];
+    unsigned long long key;
+    if (!fuse_point(A, m, g - (long long)m * HW, X) || !voxel_key(A, X, key)) return;
+    unsigned long long h = hash64(key) & A.mask;
+    for (unsigned long long probe = 0; probe <= A.mask; ++probe) {
+        const unsigned long long prev = atomicCAS(&A.keys[h], EMPTY_KEY, key);
+        if (prev == EMPTY_KEY || prev == key) {
+            atomicMin(&A.vals[h], (unsigned long long)g);
+            return;
+        }
+        h = (h + 1) & A.mask;
+    }
+}
+
+// keep = this point is the first of its voxel; the wave adds its count.
+__global__ __launch_bounds__(BLOCK) void k_fuse_mark(FuseArgs A)
+{
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long HW = (long long)A.W * A.H;
+    bool kept = false;
+    if (g < HW * A.n_maps) {
+        const int m = (int)(g / HW);
+        double X[3];
+        unsigned long long key;
+        if (fuse_point(A, m, g - (long long)m * HW, X) && voxel_key(A, X, key)) {
+            unsigned long long h = hash64(key) & A.mask;
+            for (unsigned long long probe = 0; probe <= A.mask; ++probe) {
+                if (A.keys[h] == key) {
+                    kept = A.vals[h] == (unsigned long long)g;
+                    break;
+                }
+                if (A.keys[h] == EMPTY_KEY) break;
+                h = (h + 1) & A.mask;
+            }
+        }
+        A.keep[g] = kept ? 1 : 0;
+    }
+    const unsigned long long bm = __ballot(kept);
+    if ((threadIdx.x & 63) == 0 && bm) atomicAdd(A.count, (unsigned long long)__popcll(bm));
+}
+
+__global__ __launch_bounds__(BLOCK) void k_cover_clear(FuseArgs A)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < (long long)A.Wc * A.Hc) A.cover[i] = 0;
+    if (i == 0) A.count[0] = 0ULL;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_cover_mark(FuseArgs A)
+{
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long HW = (long long)A.W * A.H;
+    if (g >= HW * A.n_maps) return;
+    if (A.keep_in && !A.keep_in[g]) return;
+    const int m = (int)(g / HW);
+    double X[3];
+    if (!fuse_point(A, m, g - (long long)m * HW, X)) return;
+    double Y[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) Y[k] = A.view.R[3 * k] * X[0] + A.view.R[3 * k + 1] * X[1] + A.view.R[3 * k + 2] * X[2] + A.view.t[k];
+    if (!(Y[0] * Y[0] + Y[1] * Y[1] + Y[2] * Y[2] > 0.0)) return;
+    const double PI = 3.14159265358979323846;
+    const double lam = atan2(Y[0], Y[2]);
+    const double phi = atan2(-Y[1], hypot(Y[0], Y[2]));
+    const double u = A.Wc * (lam + PI) / (2.0 * PI) - 0.5;
+    const double v = A.Hc * (PI / 2.0 - phi) / PI - 0.5;
+    double fx = floor(u + 0.5);
+    fx -= A.Wc * floor(fx / A.Wc);
+    int xi = (int)fx;
+    xi = xi >= A.Wc ? xi - A.Wc : (xi < 0 ? xi + A.Wc : xi);
+    const double fy = floor(v + 0.5);
+    const int yi = fy < 0.0 ? 0 : (fy > A.Hc - 1 ? A.Hc - 1 : (int)fy);
+    A.cover[(long long)yi * A.Wc + xi] = 1;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_cover_count(FuseArgs A)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool c = i < (long long)A.Wc * A.Hc && A.cover[i];
+    const unsigned long long bm = __ballot(c);
+    if ((threadIdx.x & 63) == 0 && bm) atomicAdd(A.count, (unsigned long long)__popcll(bm));
 }
 
 // Test hook: raw Philox blocks.

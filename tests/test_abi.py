@@ -41,7 +41,7 @@ def test_struct_sizes_match_c_layout(B):
     assert C.sizeof(B.Image) == 32
     assert C.sizeof(B.Plane) == 16
     assert C.sizeof(B.Pose) == 96
-    assert C.sizeof(B.Params) == 16 + 16 + 8 + 8 + 32 + 4 + 128 + 4 + 16 + 8 + 8
+    assert C.sizeof(B.Params) == 16 + 16 + 8 + 8 + 32 + 4 + 128 + 4 + 16 + 8 + 8 + 8 + 8
 
 
 def test_default_params(B):
@@ -119,6 +119,8 @@ def test_well_formed_call_reaches_the_device_step(B, vctx):
     (lambda c: setattr(c.params, "n_offsets", 17), INVALID),
     (lambda c: setattr(c.params, "ncc_var_floor", float("nan")), INVALID),
     (lambda c: setattr(c.params, "geo_px", -1.0), INVALID),
+    (lambda c: setattr(c.params, "median_radius", 9), INVALID),
+    (lambda c: setattr(c.params, "median_rel", -0.1), INVALID),
     (lambda c: setattr(c.depth, "data", None), INVALID),              # null output
     (lambda c: setattr(c.cost, "pitch_elems", 10), INVALID),
     (lambda c: setattr(c, "n_maps", 2), INVALID),                     # maps missing
@@ -167,8 +169,8 @@ def test_status_strings(B):
 
 def test_struct_sizes_of_batch_types(B):
     # pms_job: image 32 + pose 96 + 2 pointers + int (padded to 8) + 2 pointers
-    # + int (padded) + params pointer + 5 planes
-    assert C.sizeof(B.Job) == 32 + 96 + 16 + 8 + 16 + 8 + 8 + 5 * 16
+    # + int (padded) + params pointer + 5 output planes + 4 initial planes
+    assert C.sizeof(B.Job) == 32 + 96 + 16 + 8 + 16 + 8 + 8 + 5 * 16 + 4 * 16
     assert C.sizeof(B.Schedule) == 12
 
 
@@ -248,3 +250,49 @@ def test_server_entry_points_validate(B, vctx):
     assert L.pms_server_step(None, None, None, None) == INVALID
     st = C.c_int32()
     assert L.pms_server_poll(None, 1, C.byref(st)) == INVALID
+
+
+def test_warp_and_init_planes_validate(B, vctx):
+    L = B.lib()
+    c = _Call(B)
+    W, H = 64, 32
+    src = (B.Plane * 3)(B.Plane(0x20000, W), B.Plane(0x21000, W), B.Plane(0x22000, W))
+    dst = (B.Plane * 3)(B.Plane(0x30000, W), B.Plane(0x31000, W), B.Plane(0x32000, W))
+    sd, dd = B.Plane(0x23000, W), B.Plane(0x33000, W)
+    args = lambda w, h, s_d, d_d: (vctx, w, h, C.byref(c.pose), s_d, src, C.byref(c.nposes[0]),
+                                   C.byref(c.params), d_d, dst, None)
+    assert L.pms_warp_planes(*args(W, H, sd, dd)) == DEVICE
+    assert L.pms_warp_planes(*args(W, 31, sd, dd)) == INVALID
+    assert L.pms_warp_planes(*args(W, H, sd, B.Plane(0x21000, W))) == INVALID  # overlap
+    assert L.pms_warp_planes(*args(W, H, B.Plane(0x23000, 8), dd)) == INVALID  # pitch < W
+    # a job's initial planes: one pitch for all four, not an output of the batch
+    j = _job(B, c, 0x1000)
+    j.init_depth = B.Plane(0x40000, W)
+    for k in range(3):
+        j.init_normal[k] = B.Plane(0x41000 + 0x1000 * k, W)
+    jobs = (B.Job * 1)(j)
+    assert L.pms_densify_batch(vctx, jobs, 1, None) == DEVICE
+    jobs[0].init_normal[1] = B.Plane(0x42000, W + 8)
+    assert L.pms_densify_batch(vctx, jobs, 1, None) == INVALID
+    jobs[0].init_normal[1] = B.Plane(0x42000, W)
+    jobs[0].init_depth = jobs[0].depth_out
+    assert L.pms_densify_batch(vctx, jobs, 1, None) == INVALID
+
+
+def test_fusion_entry_points_validate(B, vctx):
+    L = B.lib()
+    c = _Call(B)
+    W, H = 64, 32
+    maps = (B.Plane * 2)(B.Plane(0x50000, W), B.Plane(0x51000, W))
+    poses = (B.Pose * 2)(c.pose, c.nposes[0])
+    keep, cnt = C.c_void_p(0x60000), C.c_void_p(0x61000)
+    assert L.pms_fuse(vctx, W, H, 2, maps, poses, 0.02, keep, cnt, None) == DEVICE
+    assert L.pms_fuse(vctx, W, H, 2, maps, poses, 0.0, keep, cnt, None) == INVALID
+    assert L.pms_fuse(vctx, W, H, 9, maps, poses, 0.02, keep, cnt, None) == INVALID
+    assert L.pms_fuse(vctx, W, 30, 2, maps, poses, 0.02, keep, cnt, None) == INVALID
+    assert L.pms_fuse(vctx, W, H, 2, maps, poses, 0.02, None, cnt, None) == INVALID
+    cov = C.c_void_p(0x70000)
+    assert L.pms_coverage(vctx, W, H, 2, maps, poses, keep, C.byref(c.pose), 720, 360, cov, cnt,
+                          None) == DEVICE
+    assert L.pms_coverage(vctx, W, H, 2, maps, poses, None, C.byref(c.pose), 720, 300, cov, cnt,
+                          None) == INVALID
