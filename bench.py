@@ -21,11 +21,14 @@ Two more sections ride on the same line (skip them with --no-batch /
   the autotuned tile shape, against the plain FP32 path densifying the same
   32 jobs one by one; accuracy of both against the rendered ground truth per
   resolution class, and their agreement.
-* "serving": 8 streams of Poisson(3/s) requests of uniform width and 3-6
-  neighbours (FP16) through the continuous-batching server for
-  --serve-horizon seconds of arrivals: keyframes/s, p50/p99 latency from
-  arrival to result, mean batch occupancy; three served jobs re-run alone
-  must match bit for bit.
+* "serving": 8 keyframe streams (Poisson(3/s) each, one width per stream
+  from 960/1920/2880, 3-6 neighbours, FP16) through the continuous-batching
+  server for --serve-horizon seconds of arrivals; a keyframe whose stream
+  predecessor is done starts from its warped planes (Sec. III-B) with
+  --serve-warm-iters iterations. Keyframes/s, p50/p99 latency from arrival
+  to result, mean batch occupancy, accuracy against ground truth beside the
+  plain FP32 path on the same keyframes; three served jobs re-run alone must
+  match bit for bit.
 """
 from __future__ import annotations
 
@@ -50,6 +53,13 @@ METRIC = "keyframes/s + p50/p99 latency @1920×960, 4 nbrs; NCC evals/s vs roofl
 # the NCC. Peak: 256 CUs x 64 lanes x 2.4 GHz non-packed FP32 lane-slots.
 SLOTS_PER_SAMPLE = 76
 SLOTS_PER_EVAL = 30
+# The same unit priced by the gfx950 ISA of this build's short-form sample
+# loop (about 56 VALU instructions a sample, its 3 rcp and 1 sqrt issuing at
+# half rate) and per evaluation (NCC finish, top-k, the shared view set-up
+# and its LDS exchange): an estimate of the VALU utilisation, not the
+# contract figure above.
+ISA_SLOTS_PER_SAMPLE = 60
+ISA_SLOTS_PER_EVAL = 150
 PEAK_TSLOTS = 256 * 64 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 # algorithmic HBM bytes per updated pixel of a half-sweep: own plane 16 +
@@ -75,7 +85,7 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(schedule: dict):
     """HBM bytes per half-sweep launch from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads
     for a plain copy of known size), or None when the summary is missing or
@@ -89,6 +99,8 @@ def measured_traffic():
             if line.startswith("<!-- traffic "):
                 rec = json.loads(line[len("<!-- traffic "):].rsplit("-->", 1)[0])
     if not rec or rec.get("kernel_sources") != kernel_source_hash():
+        return None
+    if rec.get("schedule") != [schedule["wave_rows"], schedule["waves_x"]]:
         return None
     return rec
 
@@ -275,54 +287,142 @@ def batch_section(args, torch, pms, synth, pool, ctx) -> dict:
 
 
 def serving_section(args, torch, pms, synth, pool, ctx) -> dict:
-    """Poisson request streams through the continuous-batching server."""
+    """Keyframe streams through the continuous-batching server. A keyframe
+    whose stream predecessor is already done starts from the predecessor's
+    planes carried over by plane-map warping (Sec. III-B) and runs
+    --serve-warm-iters iterations; otherwise it starts from random planes
+    with the full iterations. Accuracy against the rendered ground truth is
+    measured on every 8th served keyframe and on the same keyframes
+    densified by the plain FP32 path with the full iterations."""
     from paper_2211_16266_amd import serving
     dev = torch.device("cuda:0")
-    imgs = {W: [torch.from_numpy(a).to(dev).half() for a in w.images] for W, w in pool.items()}
-    reqs = synth.poisson_requests(args.serve_streams, args.serve_rate, args.serve_horizon,
-                                  seed=args.seed + 7)
-
-    def factory(mj):
-        def make():
-            w = pool[mj.W]
-            params = dict(w.params, seed=mj.seed)
-            return pms.job(imgs[mj.W][mj.ref], [imgs[mj.W][k] for k in mj.nbrs], w.poses[mj.ref],
-                           [w.poses[k] for k in mj.nbrs], params)
-        return make
-
-    requests = [serving.Request(t, factory(mj), tag=(k, mj)) for k, (t, s, mj) in enumerate(reqs)]
+    imgs32 = {W: [torch.from_numpy(a).to(dev) for a in w.images] for W, w in pool.items()}
+    imgs16 = {W: [t.half() for t in ts] for W, ts in imgs32.items()}
+    reqs = synth.stream_requests(args.serve_streams, args.serve_rate, args.serve_horizon,
+                                 seed=args.seed + 7)
+    warp_ctx = pms.Context(0)
     server = pms.Server(int(args.serve_arena_gib * 2**30), max_jobs=args.serve_max_jobs,
                         ctx=pms.Context(0))
-    check_tags = {0, len(requests) // 2, len(requests) - 1}
-    kept = {}
+    latest = {}   # stream -> (k, width, keyframe, depth, normal) of its newest finished keyframe
+    count = {"warm": 0, "cold": 0}
+    sample_every = 8
+    samples = []  # (MixedJob, warm, outputs)
+
+    def factory(i, s, k, mj):
+        def make():
+            w = pool[mj.W]
+            prev = latest.get(s)
+            init, iters = None, w.params["iterations"]
+            if not args.serve_cold and prev is not None and prev[0] == k - 1:
+                _, _, pref, pd, pn = prev
+                init = pms.warp_planes(pd, pn, w.poses[pref], w.poses[mj.ref], w.params, ctx=warp_ctx)
+                iters = args.serve_warm_iters
+            count["warm" if init is not None else "cold"] += 1
+            params = dict(w.params, seed=mj.seed, iterations=iters)
+            jd = pms.job(imgs16[mj.W][mj.ref], [imgs16[mj.W][j] for j in mj.nbrs], w.poses[mj.ref],
+                         [w.poses[j] for j in mj.nbrs], params, init=init)
+            jd.warm = init is not None
+            return jd
+        return make
+
+    requests = [serving.Request(t, factory(i, s, k, mj), tag=(i, s, k, mj))
+                for i, (t, s, k, mj) in enumerate(reqs)]
+
+    # consistency window: a finished keyframe is filtered against the depth
+    # maps of its stream's four predecessors once they are all done (the
+    # paper filters once five depth maps exist); on a copy, so the served
+    # maps stay comparable with the plain path
+    history = {}  # stream -> {k: (keyframe, depth)}
+    filt = {"filtered": 0, "kept": [], "valid": []}
+    geo_ctx = pms.Context(0)
+
+    def consistency_window(s, k, mj, jd):
+        h = history.setdefault(s, {})
+        h[k] = (mj.ref, jd.out[0])
+        for old in [j for j in h if j < k - 4]:
+            del h[old]
+        if not all(j in h for j in range(k - 4, k)):
+            return
+        w = pool[mj.W]
+        d, n, c = (t.clone() for t in jd.out)
+        maps = [h[j][1] for j in range(k - 4, k)]
+        pms.consistency(w.poses[mj.ref], maps, [w.poses[h[j][0]] for j in range(k - 4, k)],
+                        w.params, d, n, c, ctx=geo_ctx)
+        filt["filtered"] += 1
+        filt["kept"].append((d > 0).sum())
+        filt["valid"].append((jd.out[0] > 0).sum())
 
     def on_done(rq, res):
-        if rq.tag[0] in check_tags:
-            kept[rq.tag[0]] = rq.job
+        i, s, k, mj = rq.tag
+        d, n, _ = rq.job.out
+        if s not in latest or latest[s][0] < k:
+            latest[s] = (k, mj.W, mj.ref, d, n)
+        consistency_window(s, k, mj, rq.job)
+        if i % sample_every == 0:
+            samples.append((mj, rq.job.warm, rq.job))
 
-    log(f"serving {len(requests)} requests from {args.serve_streams} streams at "
-        f"{args.serve_rate}/s each over {args.serve_horizon:.0f} s")
+    log(f"serving {len(requests)} keyframes from {args.serve_streams} streams at "
+        f"{args.serve_rate}/s each over {args.serve_horizon:.0f} s "
+        f"({'random initialisation only' if args.serve_cold else 'warm starts when possible'})")
     out = serving.run(server, requests, on_done=on_done, log=log, keep_jobs=False)
     torch.cuda.synchronize()
+    # the same keyframes alone through the same path: bitwise equal
     solo_equal = True
-    for k, jd in kept.items():
-        solo = pms.densify(jd.ref, jd.nbrs, jd.ref_pose, jd.nbr_poses, jd.params, ctx=server.ctx)
+    for mj, warm, jd in samples[:3]:
+        solo = pms.densify_job(pms.job(jd.ref, jd.nbrs, jd.ref_pose, jd.nbr_poses, jd.params,
+                                       init=jd.init), ctx=server.ctx)
         torch.cuda.synchronize()
         solo_equal &= all(torch.equal(a, b) for a, b in zip(jd.out, solo))
     server.close()
+
+    # accuracy against the ground truth, and the plain FP32 path on the same keyframes
+    def gt_acc(depth, mj):
+        w = pool[mj.W]
+        r = (w.params["patch_size"] - 1) // 2
+        return _gt_accuracy(depth.cpu().numpy(), w.gt_depth[mj.ref], r)[1]
+
+    served_acc = [gt_acc(jd.out[0], mj) for mj, _, jd in samples]
+    plain_jobs = []
+    for mj, _, _ in samples:
+        w = pool[mj.W]
+        plain_jobs.append(pms.job(imgs32[mj.W][mj.ref], [imgs32[mj.W][j] for j in mj.nbrs],
+                                  w.poses[mj.ref], [w.poses[j] for j in mj.nbrs],
+                                  dict(w.params, seed=mj.seed)))
+    for jd in plain_jobs[:2]:
+        pms.densify(jd.ref, jd.nbrs, jd.ref_pose, jd.nbr_poses, jd.params, out=jd.out, ctx=ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for jd in plain_jobs:
+        pms.densify(jd.ref, jd.nbrs, jd.ref_pose, jd.nbr_poses, jd.params, out=jd.out, ctx=ctx)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    plain_acc = [gt_acc(jd.out[0], mj) for (mj, _, _), jd in zip(samples, plain_jobs)]
+    warp_ctx.close()
+    kept = float(sum(int(t.item()) for t in filt["kept"]))
+    valid = float(sum(int(t.item()) for t in filt["valid"]))
+    geo_ctx.close()
     offered = args.serve_streams * args.serve_rate
-    return {"workload": f"{args.serve_streams} streams x Poisson({args.serve_rate}/s), widths "
-                        "960/1920/2880 uniform, N~U{3..6}, f16",
+    return {"workload": f"{args.serve_streams} keyframe streams x Poisson({args.serve_rate}/s), "
+                        "one width per stream from 960/1920/2880, N~U{3..6}, f16 images",
+            "warm_start": not args.serve_cold, "warm_iterations": args.serve_warm_iters,
+            "warm_started": count["warm"], "cold_started": count["cold"],
             "horizon_s": args.serve_horizon, "requests": out["requests"],
             "offered_keyframes_per_s": offered,
             "keyframes_per_s": out["keyframes_per_s"], "wall_s": out["wall_s"],
             "latency_ms": {"p50": out["p50_ms"], "p99": out["p99_ms"], "mean": out["mean_ms"]},
             "mean_batch_occupancy": out["mean_occupancy"], "ticks": out["ticks"],
             "max_jobs": args.serve_max_jobs, "arena_peak_gib": out["arena_peak_bytes"] / 2**30,
-            "solo_rerun_bitwise_equal": bool(solo_equal), "solo_rerun_checked": len(kept)}
+            "within_1pct_of_gt": {"served": float(np.mean(served_acc)),
+                                  "plain_fp32_full_iterations": float(np.mean(plain_acc)),
+                                  "keyframes": len(samples)},
+            "plain_fp32_keyframes_per_s_on_those": len(plain_jobs) / t_plain,
+            "consistency_window": {"keyframes_filtered": filt["filtered"],
+                                   "kept_fraction_of_valid": kept / valid if valid else None},
+            "solo_rerun_bitwise_equal": bool(solo_equal), "solo_rerun_checked": min(3, len(samples))}
 
 
-def counter_summary(fetch_dir: str, write_dir: str, probe_bytes: int, commands: list) -> str:
+def counter_summary(fetch_dir: str, write_dir: str, probe_bytes: int, commands: list,
+                    schedule: list) -> str:
     """Writes the HBM traffic summary of the half-sweep kernel from two
     rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; csv) of this benchmark with
     --copy-probe, each counter scaled by what it reads for the probe copy."""
@@ -349,7 +449,8 @@ def counter_summary(fetch_dir: str, write_dir: str, probe_bytes: int, commands: 
                         "probe_kib": probe, "scale": probe_bytes / 1024.0 / probe}
     fetch = out["FETCH_SIZE"]["halfsweep_kib"] * out["FETCH_SIZE"]["scale"] * 1024
     write = out["WRITE_SIZE"]["halfsweep_kib"] * out["WRITE_SIZE"]["scale"] * 1024
-    rec = {"kernel_sources": kernel_source_hash(), "bytes_per_launch": fetch + write,
+    rec = {"kernel_sources": kernel_source_hash(), "schedule": schedule,
+           "bytes_per_launch": fetch + write,
            "fetch_bytes": fetch, "write_bytes": write,
            "fetch_kib_raw": out["FETCH_SIZE"]["halfsweep_kib"],
            "write_kib_raw": out["WRITE_SIZE"]["halfsweep_kib"],
@@ -371,8 +472,9 @@ def counter_summary(fetch_dir: str, write_dir: str, probe_bytes: int, commands: 
         f"{probe_bytes / 1024:.0f} KiB | {rec['write_scale']:.3f} | {write / 1e6:.1f} MB |",
         "",
         f"Traffic per half-sweep launch: {(fetch + write) / 1e6:.1f} MB over "
-        f"{rec['dispatches']} dispatches; kernel sources {rec['kernel_sources']} (the benchmark",
-        "reports this figure only while the sources hash the same).",
+        f"{rec['dispatches']} dispatches; kernel sources {rec['kernel_sources']}, tile shape "
+        f"{schedule[0]},{schedule[1]} (the benchmark reports this figure only for the same sources "
+        "and shape).",
         "",
         "<!-- traffic " + json.dumps(rec) + " -->",
         "",
@@ -392,6 +494,9 @@ def main() -> int:
     ap.add_argument("--cpu-budget", type=float, default=12.0,
                     help="wall seconds of oracle work for the CPU baseline (0 = skip)")
     ap.add_argument("--no-batch", action="store_true", help="skip the mixed FP16 batch section")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default tile shape")
+    ap.add_argument("--schedule", default=None, metavar="WAVE_ROWS,WAVES_X",
+                    help="use this tile shape instead of autotuning (e.g. 4,2)")
     ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--serve-horizon", type=float, default=20.0,
                     help="seconds of request arrivals in the serving section (0 = skip)")
@@ -399,19 +504,25 @@ def main() -> int:
     ap.add_argument("--serve-streams", type=int, default=8)
     ap.add_argument("--serve-max-jobs", type=int, default=8)
     ap.add_argument("--serve-arena-gib", type=float, default=16.0)
+    ap.add_argument("--serve-cold", action="store_true",
+                    help="random initialisation for every served keyframe (no plane-map warping)")
+    ap.add_argument("--serve-warm-iters", type=int, default=2,
+                    help="iterations of a keyframe that starts from its predecessor's warped planes")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="bytes of a plain device-to-device copy run once before the "
                          "timed region, to calibrate HBM byte counters (0 = none)")
-    ap.add_argument("--counter-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+    ap.add_argument("--counter-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "SCHEDULE"),
                     help="write the traffic summary from two rocprofv3 --pmc csv directories "
                          "(no GPU needed) and exit")
     args = ap.parse_args()
     if args.counter_summary:
+        fetch_dir, write_dir, sched = args.counter_summary
         cmd = ("rocprofv3 --pmc {c} --output-format csv -d gpurun_out/pmc_{c} -o pmc -- python3 "
                "bench.py --steps 2 --warmup 0 --cpu-budget 0 --no-batch --serve-horizon 0 "
-               "--copy-probe 268435456")
-        print(counter_summary(*args.counter_summary, 268435456,
-                              [cmd.format(c="FETCH_SIZE"), cmd.format(c="WRITE_SIZE")]))
+               "--copy-probe 268435456 --schedule " + sched)
+        print(counter_summary(fetch_dir, write_dir, 268435456,
+                              [cmd.format(c="FETCH_SIZE"), cmd.format(c="WRITE_SIZE")],
+                              [int(v) for v in sched.split(",")]))
         return 0
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the densifier runs one keyframe job per GPU "
@@ -452,6 +563,16 @@ def main() -> int:
 
     def step():
         pms.densify(ref, nbrs, rp, nps, params, maps=maps, map_poses=map_poses, out=out, ctx=ctx)
+
+    if args.schedule:
+        wr, wx = (int(v) for v in args.schedule.split(","))
+        ctx.set_schedule(wave_rows=wr, waves_x=wx)
+    schedule = ctx.get_schedule()
+    if not args.no_tune and not args.schedule:
+        # tile shapes never change a result, only the speed
+        log("autotuning the tile shape on this keyframe")
+        schedule, tune_ms = ctx.autotune([pms.job(ref, nbrs, rp, nps, params)], reps=1)
+        log(f"schedule {schedule}: {tune_ms:.1f} ms of init + half-sweeps")
 
     if args.copy_probe > 0:
         n = args.copy_probe // 4
@@ -500,7 +621,7 @@ def main() -> int:
     achieved = slots_per_launch / avg_half_s / 1e12
     img_bytes = (N + 1) * W * H * w.images[0].itemsize
     hbm_bytes = (vpx // 2) * HBM_BYTES_PER_UPDATE + img_bytes
-    traffic = measured_traffic()
+    traffic = measured_traffic(schedule)
 
     result = {
         "metric": METRIC,
@@ -521,7 +642,7 @@ def main() -> int:
                             f"{params['patch_stride']} ({P} samples)",
                    "iterations": params["iterations"], "refine_trials": params["refine_trials"],
                    "depth_range_m": [params["depth_min"], params["depth_max"]],
-                   "consistency_maps": len(maps), "seed": args.seed},
+                   "consistency_maps": len(maps), "seed": args.seed, "schedule": schedule},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "mean": float(lat.mean())},
         "ncc_evals_per_s": evals_per_kf * kfps,
@@ -539,6 +660,8 @@ def main() -> int:
             "launches": n_half,
             "algorithmic_per_launch": {"ncc_evals": evals_per_launch, "slots": slots_per_launch,
                                        "hbm_bytes": hbm_bytes},
+            "isa_priced_frac": evals_per_launch * (P * ISA_SLOTS_PER_SAMPLE + ISA_SLOTS_PER_EVAL)
+                               / avg_half_s / 1e12 / PEAK_TSLOTS,
             "hbm_achieved_GBs": hbm_bytes / avg_half_s / 1e9,
             "hbm_frac": hbm_bytes / avg_half_s / 1e9 / HBM_PEAK_GBS,
         },

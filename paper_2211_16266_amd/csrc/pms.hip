@@ -545,6 +545,8 @@ void fill_sweep_args(pms::SweepArgs &A, const JobSpec &J, const Geometry &g, con
     A.tiles_x_all = g.tiles_x_all;
     A.tiles_x_half = g.tiles_x_half;
     A.ref_dtype = J.ref->dtype;
+    // the half-sweep test hook starts from caller-given costs
+    A.own_costs = J.mode == MODE_SWEEP ? 0 : 1;
     A.ref.ptr = J.ref->data;
     A.ref.pitch = J.ref->pitch_bytes;
     for (int j = 0; j < J.n_nbrs; ++j) {

@@ -106,6 +106,7 @@ struct SweepArgs {
     int tiles_x_all;         // tiles per tile row over all pixels
     int tiles_x_half;        // ... over the pixels of one colour
     int ref_dtype;
+    int own_costs;           // stored costs were computed by these kernels
     ImgRef ref;
     ViewPoseD pose[MAXV];    // relative poses in FP64 (warped centre ray)
     ViewPoseF posef[MAXV];   // the same rounded (homography on offsets)
@@ -973,7 +974,10 @@ __device__ __forceinline__ void halfsweep_tile(const SweepArgs &A, int tile, int
         if (!(den < 0.0f)) continue;
         const float dd = cq / den;
         if (!(dd >= A.dmin && dd <= A.dmax)) continue;
-        const bool same_best = __float_as_uint(dd) == __float_as_uint(bd) && __float_as_uint(sq.x) == __float_as_uint(bn0) &&
+        // (the stored cost of the current plane is this evaluation's result
+        // only when these kernels computed it)
+        const bool same_best = (A.own_costs || bd != cur.w || bn0 != cur.x || bn1 != cur.y || bn2 != cur.z) &&
+                               __float_as_uint(dd) == __float_as_uint(bd) && __float_as_uint(sq.x) == __float_as_uint(bn0) &&
                                __float_as_uint(sq.y) == __float_as_uint(bn1) && __float_as_uint(sq.z) == __float_as_uint(bn2);
         const bool same_prev = __float_as_uint(dd) == __float_as_uint(pd) && __float_as_uint(sq.x) == __float_as_uint(pn0) &&
                                __float_as_uint(sq.y) == __float_as_uint(pn1) && __float_as_uint(sq.z) == __float_as_uint(pn2);

@@ -432,3 +432,30 @@ def poisson_requests(n_streams: int, rate_hz: float, horizon_s: float, seed: int
             out.append((float(t), s, _mixed_job(rng, W, n_range, n_kf)))
             t += rng.exponential(1.0 / rate_hz)
     return sorted(out, key=lambda r: r[0])
+
+
+def stream_requests(n_streams: int, rate_hz: float, horizon_s: float, seed: int = 0,
+                    widths=MIXED_WIDTHS, n_range=(3, 6), n_kf: int = 7) -> list:
+    """Keyframe streams for a serving loop: each stream has one width (drawn
+    uniformly from `widths`) and walks the keyframes of its window back and
+    forth (0, 1, ..., n_kf-1, n_kf-2, ..., 0, 1, ...), so consecutive
+    keyframes of a stream are neighbours along the trajectory; arrivals are
+    Poisson with rate_hz; each keyframe takes N ~ U{n_range} neighbours
+    nearest to it. Returns sorted (time, stream, k, MixedJob), k = the
+    keyframe's position in its stream."""
+    rng = np.random.default_rng(seed)
+    out = []
+    period = 2 * (n_kf - 1)
+    for s in range(n_streams):
+        W = int(widths[int(rng.integers(0, len(widths)))])
+        t = rng.exponential(1.0 / rate_hz)
+        k = 0
+        while t < horizon_s:
+            ph = k % period
+            ref = ph if ph < n_kf else period - ph
+            N = int(rng.integers(n_range[0], n_range[1] + 1))
+            others = sorted((j for j in range(n_kf) if j != ref), key=lambda j: (abs(j - ref), j))[:N]
+            out.append((float(t), s, k, MixedJob(W, ref, sorted(others), int(rng.integers(1 << 31)))))
+            t += rng.exponential(1.0 / rate_hz)
+            k += 1
+    return sorted(out, key=lambda r: r[0])

@@ -77,8 +77,9 @@ def test_admission_respects_the_arena(pms, pool):
     H = W // 2
     mjs = [synth.MixedJob(W, 3, [1, 2, 4, 5], seed=k) for k in range(5)]
     state = H * W * (16 + 4 + 8)
-    pad = (H + 2) * (2 * W + 4) * 2
-    arena = int(2.3 * state) + 6 * pad + (64 << 10)
+    pad = (H + 2) * (2 * W + 4) * 8  # re-laid-out copies: (value, difference) in FP32
+    # the four shared neighbour copies and room for two jobs' state, not three
+    arena = int(2.5 * state) + 4 * pad + (64 << 10)
     server = pms.Server(arena_bytes=max(arena, 1 << 20), max_jobs=8, ctx=ctx)
     # a job that can never fit
     big_pool = synth.mixed_pool(seed=4, widths=(512,), dtype="f16")
@@ -107,5 +108,43 @@ def test_admission_respects_the_arena(pms, pool):
     assert st["arena_peak"] <= max(arena, 1 << 20)
     for jd in jds:
         assert (jd.out[0] > 0).float().mean() > 0.3
+    server.close()
+    ctx.close()
+
+
+def test_served_jobs_with_initial_planes_equal_solo_runs(pms, pool):
+    """Jobs that start from warped planes (Sec. III-B) inside the server."""
+    from helpers import bearings
+    dev = _tensors(pool)
+    ctx = pms.Context(0)
+    server = pms.Server(arena_bytes=64 << 20, max_jobs=4, ctx=ctx)
+    jobs = []
+    for W in (128, 192, 256):
+        w = pool[W]
+        for ref, prev in ((3, 2), (4, 3)):
+            d = torch.from_numpy(w.gt_depth[prev]).cuda()
+            n = w.gt_normal[prev].copy()
+            flip = (n * bearings(w.W, w.H)).sum(0) > 0
+            n[:, flip] *= -1
+            init = pms.warp_planes(d, torch.from_numpy(n).cuda(), w.poses[prev], w.poses[ref],
+                                   w.params, ctx=ctx)
+            nb = [k for k in range(7) if k != ref][:4]
+            jobs.append(pms.job(dev[W][ref], [dev[W][k] for k in nb], w.poses[ref],
+                                [w.poses[k] for k in nb], dict(w.params, iterations=2), init=init))
+    say("serving 6 warm-started jobs")
+    tickets = [server.submit(jd) for jd in jobs]
+    pending = set(tickets)
+    for _ in range(100):
+        server.step()
+        pending = {t for t in pending if server.poll(t) != pms.Server.DONE}
+        if not pending:
+            break
+    torch.cuda.synchronize()
+    assert not pending
+    for jd in jobs:
+        solo = pms.densify_job(pms.job(jd.ref, jd.nbrs, jd.ref_pose, jd.nbr_poses, jd.params,
+                                       init=jd.init), ctx=ctx)
+        torch.cuda.synchronize()
+        assert all(torch.equal(a, b) for a, b in zip(jd.out, solo))
     server.close()
     ctx.close()
