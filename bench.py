@@ -286,7 +286,7 @@ def batch_section(args, torch, pms, synth, pool, ctx) -> dict:
                                 "speedup": t_small_plain / t_small_batch}}
 
 
-def serving_section(args, torch, pms, synth, pool, ctx) -> dict:
+def serving_section(args, torch, pms, synth, pool, ctx, warm: bool) -> dict:
     """Keyframe streams through the continuous-batching server. A keyframe
     whose stream predecessor is already done starts from the predecessor's
     planes carried over by plane-map warping (Sec. III-B) and runs
@@ -313,7 +313,7 @@ def serving_section(args, torch, pms, synth, pool, ctx) -> dict:
             w = pool[mj.W]
             prev = latest.get(s)
             init, iters = None, w.params["iterations"]
-            if not args.serve_cold and prev is not None and prev[0] == k - 1:
+            if warm and prev is not None and prev[0] == k - 1:
                 _, _, pref, pd, pn = prev
                 init = pms.warp_planes(pd, pn, w.poses[pref], w.poses[mj.ref], w.params, ctx=warp_ctx)
                 iters = args.serve_warm_iters
@@ -361,10 +361,16 @@ def serving_section(args, torch, pms, synth, pool, ctx) -> dict:
         if i % sample_every == 0:
             samples.append((mj, rq.job.warm, rq.job))
 
+    def ready(rq):
+        # a keyframe waits for its stream predecessor, whose planes it starts from
+        i, s, k, mj = rq.tag
+        return k == 0 or (s in latest and latest[s][0] >= k - 1)
+
     log(f"serving {len(requests)} keyframes from {args.serve_streams} streams at "
         f"{args.serve_rate}/s each over {args.serve_horizon:.0f} s "
-        f"({'random initialisation only' if args.serve_cold else 'warm starts when possible'})")
-    out = serving.run(server, requests, on_done=on_done, log=log, keep_jobs=False)
+        f"({'warm starts from the stream predecessor' if warm else 'random initialisation'})")
+    out = serving.run(server, requests, on_done=on_done, log=log, keep_jobs=False,
+                      ready=ready if warm else None)
     torch.cuda.synchronize()
     # the same keyframes alone through the same path: bitwise equal
     solo_equal = True
@@ -404,7 +410,7 @@ def serving_section(args, torch, pms, synth, pool, ctx) -> dict:
     offered = args.serve_streams * args.serve_rate
     return {"workload": f"{args.serve_streams} keyframe streams x Poisson({args.serve_rate}/s), "
                         "one width per stream from 960/1920/2880, N~U{3..6}, f16 images",
-            "warm_start": not args.serve_cold, "warm_iterations": args.serve_warm_iters,
+            "warm_start": warm, "warm_iterations": args.serve_warm_iters if warm else None,
             "warm_started": count["warm"], "cold_started": count["cold"],
             "horizon_s": args.serve_horizon, "requests": out["requests"],
             "offered_keyframes_per_s": offered,
@@ -498,14 +504,14 @@ def main() -> int:
     ap.add_argument("--schedule", default=None, metavar="WAVE_ROWS,WAVES_X",
                     help="use this tile shape instead of autotuning (e.g. 4,2)")
     ap.add_argument("--batch-reps", type=int, default=3)
-    ap.add_argument("--serve-horizon", type=float, default=20.0,
+    ap.add_argument("--serve-horizon", type=float, default=15.0,
                     help="seconds of request arrivals in the serving section (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=3.0, help="arrivals per second per stream")
     ap.add_argument("--serve-streams", type=int, default=8)
     ap.add_argument("--serve-max-jobs", type=int, default=8)
     ap.add_argument("--serve-arena-gib", type=float, default=16.0)
     ap.add_argument("--serve-cold", action="store_true",
-                    help="random initialisation for every served keyframe (no plane-map warping)")
+                    help="serve with random initialisation only (skip the warm-start run)")
     ap.add_argument("--serve-warm-iters", type=int, default=2,
                     help="iterations of a keyframe that starts from its predecessor's warped planes")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -673,7 +679,10 @@ def main() -> int:
     if not args.no_batch:
         result["batch"] = batch_section(args, torch, pms, synth, pool, ctx)
     if args.serve_horizon > 0:
-        result["serving"] = serving_section(args, torch, pms, synth, pool, ctx)
+        result["serving"] = serving_section(args, torch, pms, synth, pool, ctx, warm=not args.serve_cold)
+        if not args.serve_cold:
+            result["serving_random_init"] = serving_section(args, torch, pms, synth, pool, ctx,
+                                                            warm=False)
     if args.cpu_budget > 0:
         threads = min(os.cpu_count() or 1, 16)
         log(f"cpu baseline: oracle on {threads} threads, ~{args.cpu_budget:.0f} s")

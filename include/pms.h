@@ -69,6 +69,7 @@ typedef enum { PMS_F32 = 0, PMS_F16 = 1, PMS_U8 = 2 } pms_dtype;
 #define PMS_MAX_SAMPLES 64   /* samples per patch                          */
 #define PMS_MAX_TRIALS 16    /* refinement trials per pixel and sweep      */
 #define PMS_MAX_BATCH 256    /* jobs per batch                             */
+#define PMS_MAX_TOP_K 4      /* views averaged (top_k, or ceil(N/2))       */
 
 typedef struct {
     const void *data;    /* device pointer                                 */
@@ -96,7 +97,8 @@ typedef struct {
     int32_t refine_trials; /* random refinement trials per pixel per sweep */
     double depth_min;      /* 0 < depth_min < depth_max, metres            */
     double depth_max;
-    int32_t top_k;         /* views averaged; 0 => ceil(N/2)                */
+    int32_t top_k;         /* views averaged; 0 => ceil(N/2); at most
+                              PMS_MAX_TOP_K (PMS_ERR_UNSUPPORTED above)     */
     double ncc_var_floor;  /* a view whose patch variance is below this is
                               invalid (cost 2)                              */
     double refine_sigma_logdepth0; /* <= 0 => 0.5 ln(depth_max/depth_min)   */

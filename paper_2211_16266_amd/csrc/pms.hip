@@ -146,6 +146,10 @@ bool check_params(pms_context *ctx, const pms_params *p, int W, int H, int n_vie
     if (!(p->depth_min > 0.0) || !(p->depth_max > p->depth_min) || !std::isfinite(p->depth_max))
         return bad("need 0 < depth_min < depth_max < inf");
     if (n_views > 0 && (p->top_k < 0 || p->top_k > n_views)) return bad("top_k out of range");
+    if (p->top_k > PMS_MAX_TOP_K || (p->top_k == 0 && (n_views + 1) / 2 > PMS_MAX_TOP_K)) {
+        *st = fail(ctx, PMS_ERR_UNSUPPORTED, "more than 4 views averaged");
+        return false;
+    }
     if (!(p->ncc_var_floor >= 0.0) || !std::isfinite(p->ncc_var_floor)) return bad("bad ncc_var_floor");
     if (!std::isfinite(p->refine_sigma_logdepth0) || !(p->refine_depth_shrink > 0.0) ||
         !std::isfinite(p->refine_depth_shrink) || !(p->refine_sigma_normal0 >= 0.0) ||

@@ -54,6 +54,7 @@
 namespace pms {
 
 constexpr int MAXV = 8;       // neighbour views per launch
+constexpr int MAXK = 4;       // views averaged (top_k)
 constexpr int MAXOFF = 16;    // propagation offsets
 constexpr int MAXTRIAL = 16;  // refinement trials
 constexpr int BLOCK = 256;    // threads per workgroup (4 waves)
@@ -518,20 +519,22 @@ __device__ __forceinline__ float evaluate(const SweepArgs &A, const Patch<SPL> &
             for (int j = 0; j < A.n_views; ++j) A.view_out[j][out_index] = 2.0f;
         return 2.0f;
     }
-    const double mc = -c64;
     const int rowb = A.Wp * (int)sizeof(PT);
     // the top_k smallest view costs, ascending, as bit patterns: costs are
     // non-negative floats, whose order is that of their bits as unsigned
-    unsigned top[MAXV];
+    unsigned top[MAXK];
 #pragma unroll
-    for (int i = 0; i < MAXV; ++i) top[i] = 0x40400000u;  // 3.0f
+    for (int i = 0; i < MAXK; ++i) top[i] = 0x40400000u;  // 3.0f
 
     __shared__ SetupLds setup_lds;
     const int slot0 = (int)threadIdx.x - lane;  // slot of the pixel's first lane
     for (int jb = 0; jb < A.n_views; jb += LPP) {
         if (jb + lane < A.n_views) {
+            // (recomputed per round rather than kept live across the
+            // sample loops)
+            const double nbp_r = (double)n0 * pt.bp64[0] + (double)n1 * pt.bp64[1] + (double)n2 * pt.bp64[2];
             ViewSetup mine;
-            view_setup<SPL>(A, pt, jb + lane, mc, nbp, n0, n1, n2, mine);
+            view_setup<SPL>(A, pt, jb + lane, -((double)d * nbp_r), nbp_r, n0, n1, n2, mine);
             put_setup(setup_lds, threadIdx.x, mine);
         }
         __builtin_amdgcn_wave_barrier();
@@ -624,32 +627,22 @@ __device__ __forceinline__ float evaluate(const SweepArgs &A, const Patch<SPL> &
             if (VIEWS && lane == 0) A.view_out[j][out_index] = cj;
             // the next round overwrites the slots read above
             __builtin_amdgcn_wave_barrier();
-            // insertion into the ascending list of the smallest costs so
+            // insertion into the ascending list of the MAXK smallest costs so
             // far; slots past top_k only collect larger costs and are never
-            // summed, so the list is kept 4 long whenever top_k <= 4 (a
-            // wave-uniform choice)
+            // summed
             unsigned cb = __float_as_uint(cj);
-            if (A.top_k <= 4) {
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const unsigned lo = min(top[i], cb), hi = max(top[i], cb);
-                    top[i] = lo;
-                    cb = hi;
-                }
-            } else {
-#pragma unroll
-                for (int i = 0; i < MAXV; ++i) {
-                    const unsigned lo = min(top[i], cb), hi = max(top[i], cb);
-                    top[i] = lo;
-                    cb = hi;
-                }
+            for (int i = 0; i < MAXK; ++i) {
+                const unsigned lo = min(top[i], cb), hi = max(top[i], cb);
+                top[i] = lo;
+                cb = hi;
             }
             if (!VIEWS) {
                 const int have = A.top_k - (A.n_views - 1 - j);  // evaluated costs in the bound
                 if (have > 0) {
                     float lb = 0.0f;
 #pragma unroll
-                    for (int i = 0; i < MAXV; ++i) {
+                    for (int i = 0; i < MAXK; ++i) {
                         if (i >= have) break;
                         lb += __uint_as_float(top[i]);
                     }
@@ -661,7 +654,7 @@ __device__ __forceinline__ float evaluate(const SweepArgs &A, const Patch<SPL> &
     // the mean as sum x fl(1/k): monotone in the sum like the bound above
     float acc = 0.0f;
 #pragma unroll
-    for (int i = 0; i < MAXV; ++i) {
+    for (int i = 0; i < MAXK; ++i) {
         if (i >= A.top_k) break;
         acc += __uint_as_float(top[i]);
     }
@@ -960,6 +953,7 @@ __device__ __forceinline__ void halfsweep_tile(const SweepArgs &A, int tile, int
     // plane, scores exactly the same cost again and cannot win under the
     // strict rule, so it is not evaluated a second time)
     float pd = -1.0f, pn0 = 0.0f, pn1 = 0.0f, pn2 = 0.0f;
+    bool loaded = true;  // the current plane is still the one read from the state
     for (int o = 0; o < A.n_offsets; ++o) {
         int qx = x + A.off_x[o];
         qx = qx < 0 ? qx + A.W : (qx >= A.W ? qx - A.W : qx);
@@ -976,7 +970,7 @@ __device__ __forceinline__ void halfsweep_tile(const SweepArgs &A, int tile, int
         if (!(dd >= A.dmin && dd <= A.dmax)) continue;
         // (the stored cost of the current plane is this evaluation's result
         // only when these kernels computed it)
-        const bool same_best = (A.own_costs || bd != cur.w || bn0 != cur.x || bn1 != cur.y || bn2 != cur.z) &&
+        const bool same_best = (A.own_costs || !loaded) &&
                                __float_as_uint(dd) == __float_as_uint(bd) && __float_as_uint(sq.x) == __float_as_uint(bn0) &&
                                __float_as_uint(sq.y) == __float_as_uint(bn1) && __float_as_uint(sq.z) == __float_as_uint(bn2);
         const bool same_prev = __float_as_uint(dd) == __float_as_uint(pd) && __float_as_uint(sq.x) == __float_as_uint(pn0) &&
@@ -993,6 +987,7 @@ __device__ __forceinline__ void halfsweep_tile(const SweepArgs &A, int tile, int
             bn0 = sq.x;
             bn1 = sq.y;
             bn2 = sq.z;
+            loaded = false;
         }
     }
 

@@ -37,29 +37,42 @@ class Result:
 
 
 def run(server: Server, requests: list[Request], stream=None, on_done=None,
-        progress_every_s: float = 10.0, log=None, keep_jobs: bool = True) -> dict:
+        progress_every_s: float = 10.0, log=None, keep_jobs: bool = True, ready=None) -> dict:
     """Serves `requests` in real time; returns the per-request results and
     the summary (throughput, p50/p99 latency, mean batch occupancy).
 
     ``on_done(request, result)`` is called once per request when it is done
     (the job's output tensors are final then). With ``keep_jobs`` False the
-    request drops its job after that call, which frees its tensors."""
+    request drops its job after that call, which frees its tensors.
+    ``ready(request)``, if given, holds an arrived request back until it
+    returns True (e.g. until the keyframe it starts from is done); held
+    requests are submitted in arrival order, and their latency still counts
+    from arrival."""
     reqs = sorted(requests, key=lambda r: r.arrival_s)
     inflight: dict[int, tuple[Request, float]] = {}
     results: list[Result] = []
     i = 0
     t0 = time.perf_counter()
     next_report = progress_every_s
-    while i < len(reqs) or inflight:
+    held: list[Request] = []
+    while i < len(reqs) or inflight or held:
         now = time.perf_counter() - t0
         while i < len(reqs) and reqs[i].arrival_s <= now:
-            if not isinstance(reqs[i].job, JobDesc):
-                reqs[i].job = reqs[i].job()
-            tk = server.submit(reqs[i].job)
-            inflight[tk] = (reqs[i], now)
+            held.append(reqs[i])
             i += 1
+        still = []
+        for rq in held:
+            if ready is not None and not ready(rq):
+                still.append(rq)
+                continue
+            if not isinstance(rq.job, JobDesc):
+                rq.job = rq.job()
+            tk = server.submit(rq.job)
+            inflight[tk] = (rq, now)
+        held = still
         if not inflight:
-            time.sleep(max(0.0, min(reqs[i].arrival_s - now, 0.05)))
+            nxt = reqs[i].arrival_s - now if i < len(reqs) else 0.001
+            time.sleep(max(0.0, min(nxt, 0.05)))
             continue
         active, _ = server.step(stream)
         now = time.perf_counter() - t0
