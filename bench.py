@@ -23,12 +23,15 @@ Two more sections ride on the same line (skip them with --no-batch /
   resolution class, and their agreement.
 * "serving": 8 keyframe streams (Poisson(3/s) each, one width per stream
   from 960/1920/2880, 3-6 neighbours, FP16) through the continuous-batching
-  server for --serve-horizon seconds of arrivals; a keyframe whose stream
-  predecessor is done starts from its warped planes (Sec. III-B) with
-  --serve-warm-iters iterations. Keyframes/s, p50/p99 latency from arrival
-  to result, mean batch occupancy, accuracy against ground truth beside the
-  plain FP32 path on the same keyframes; three served jobs re-run alone must
-  match bit for bit.
+  server for --serve-horizon seconds of arrivals. Each stream's keyframes
+  are densified in order, each starting from its predecessor's warped
+  planes (Sec. III-B) with --serve-warm-iters iterations, and filtered
+  against the stream's four previous depth maps. Keyframes/s, p50/p99
+  latency from arrival to result, mean batch occupancy, accuracy against
+  ground truth beside the plain FP32 path on the same keyframes; three
+  served jobs re-run alone must match bit for bit.
+* "serving_random_init": the same request stream with random
+  initialisation and the full iterations for every keyframe.
 """
 from __future__ import annotations
 
