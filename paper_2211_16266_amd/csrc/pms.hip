@@ -221,6 +221,10 @@ bool check_ref_and_views(pms_context *ctx, const pms_image *ref, const pms_pose 
         *st = fail(ctx, PMS_ERR_INVALID_ARG, "images must be W x H with W == 2H >= 2");
         return false;
     }
+    if (H > PMS_MAX_HEIGHT) {
+        *st = fail(ctx, PMS_ERR_INVALID_ARG, "image height above PMS_MAX_HEIGHT");
+        return false;
+    }
     if (dtype_size(ref->dtype) == 0) {
         *st = fail(ctx, PMS_ERR_INVALID_ARG, "unknown dtype");
         return false;

@@ -941,7 +941,9 @@ __device__ __forceinline__ void halfsweep_tile(const SweepArgs &A, int tile, int
     const int y = A.r + ty * A.tile_h + dy;
     if (k >= (A.W >> 1) || y > A.H - 1 - A.r) return;
     const int x = 2 * k + ((y + colour) & 1);
-    const long long idx = (long long)y * A.W + x;
+    // (32 bits: images hold fewer than 2^31 pixels; one register less to
+    // keep through the evaluations)
+    const unsigned idx = (unsigned)y * (unsigned)A.W + (unsigned)x;
 
     Patch<SPL> pt;
     patch_setup<TR, LPP, SPL>(A, x, y, lane, pt);
@@ -991,10 +993,28 @@ __device__ __forceinline__ void halfsweep_tile(const SweepArgs &A, int tile, int
         }
     }
 
+    // The draws of a trial do not depend on earlier trials: each of the LPP
+    // lanes of the pixel computes every LPP-th trial's Philox block and
+    // stages it in LDS, and the trial reads its four uniforms from the slot
+    // of the lane that drew them (the lanes of a pixel always take the same
+    // branches; only lanes of one wave exchange data, in order).
+    __shared__ float4 draws_lds[BLOCK];
+    const int slot0 = (int)threadIdx.x - lane;
     for (int t = 0; t < A.refine_trials; ++t) {
-        float u[4];
-        uniforms(A.seed, (unsigned long long)idx, (unsigned long long)iteration,
-                 (unsigned long long)(16 + t), u);
+        const int j = t & (LPP - 1);
+        if (j == 0) {
+            // (opaque, so that the first round's products are recomputed
+            // here rather than held in registers through the evaluations)
+            unsigned pix = idx;
+            asm volatile("" : "+v"(pix));
+            float drawn[4];
+            uniforms(A.seed, (unsigned long long)pix, (unsigned long long)iteration, (unsigned long long)(16 + t + lane), drawn);
+            __builtin_amdgcn_wave_barrier();
+            draws_lds[threadIdx.x] = make_float4(drawn[0], drawn[1], drawn[2], drawn[3]);
+            __builtin_amdgcn_wave_barrier();
+        }
+        const float4 uv = draws_lds[slot0 + j];
+        const float u[4] = {uv.x, uv.y, uv.z, uv.w};
         float dd = bd * expf((2.0f * u[0] - 1.0f) * A.sd[t]);
         dd = fminf(fmaxf(dd, A.dmin), A.dmax);
         float m0 = fmaf(A.sn[t], 2.0f * u[1] - 1.0f, bn0);
