@@ -12,8 +12,8 @@
  *
  * Conventions shared by every call
  * --------------------------------
- * Images:  W x H with W == 2H, H <= PMS_MAX_HEIGHT (fewer than 2^31
- *          pixels), row-major, one channel, pitch in bytes.
+ * Images:  W x H with W == 2H, H <= PMS_MAX_HEIGHT, row-major, one
+ *          channel, pitch in bytes.
  *          float32, float16 or uint8 (uint8 is scaled by 1/255; the NCC
  *          variance floor applies to the scaled values). All images of one
  *          call have the same W and H.
@@ -71,7 +71,9 @@ typedef enum { PMS_F32 = 0, PMS_F16 = 1, PMS_U8 = 2 } pms_dtype;
 #define PMS_MAX_TRIALS 16    /* refinement trials per pixel and sweep      */
 #define PMS_MAX_BATCH 256    /* jobs per batch                             */
 #define PMS_MAX_TOP_K 4      /* views averaged (top_k, or ceil(N/2))       */
-#define PMS_MAX_HEIGHT 32767 /* image rows (W = 2H, so W H < 2^31)         */
+#define PMS_MAX_HEIGHT 5790  /* image rows: a neighbour's re-laid-out copy,
+                                (H + 1) x (2W + 4) cells of 16 bytes, stays
+                                under 2 GiB (32-bit byte offsets)          */
 
 typedef struct {
     const void *data;    /* device pointer                                 */

@@ -286,9 +286,11 @@ pms::ViewPoseF relative_pose(const pms_pose &ref, const pms_pose &nbr)
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// Bytes per position of a re-laid-out image: (value, difference to the next
-// column) in FP32 whatever the input type.
-size_t pad_elem_size(int) { return sizeof(float2); }
+// A re-laid-out image holds, for every bilinear cell, the corner value and
+// its three differences in FP32 whatever the input type: (H + 1) rows of
+// 2W + 4 cells of 16 bytes.
+size_t pad_elem_size(int) { return sizeof(float4); }
+long long pad_cells(int W, int H) { return (long long)(H + 1) * (2 * (long long)W + 4); }
 
 pms_status set_device(pms_context *ctx)
 {
@@ -562,7 +564,7 @@ void fill_sweep_args(pms::SweepArgs &A, const JobSpec &J, const Geometry &g, con
         A.posef[j] = relative_pose(*J.ref_pose, J.nbr_poses[j]);
     }
     A.Wp = 2 * W + 4;
-    A.pad_bytes = (int)((size_t)(H + 2) * A.Wp * pad_elem_size(J.ref->dtype));
+    A.pad_bytes = (int)((size_t)pad_cells(W, H) * pad_elem_size(J.ref->dtype));
     A.tab_row = T.row;
     A.tab_col = T.col;
     A.tab_row64 = T.row64;
@@ -683,7 +685,7 @@ pms_status build_plan(pms_context *ctx, const std::vector<JobSpec> &specs, char 
     {
         Items items;
         for (size_t k = 0; k < P.pads.size(); ++k)
-            items.emplace_back((int)k, (int)blocks_of((long long)(P.pads[k].H + 2) * P.pads[k].Wp), 0, 0);
+            items.emplace_back((int)k, (int)blocks_of(pad_cells(P.pads[k].W, P.pads[k].H)), 0, 0);
         add_rec(P, KK_IO, IO_PAD, 0, none, items);
     }
     {
@@ -808,7 +810,7 @@ pms_status build_plan(pms_context *ctx, const std::vector<JobSpec> &specs, char 
     }
     for (auto &pj : P.pads) {
         pj.dst = base + off;
-        off += align256((size_t)(pj.H + 2) * pj.Wp * pad_elem_size(pj.dtype));
+        off += align256((size_t)pad_cells(pj.W, pj.H) * pad_elem_size(pj.dtype));
     }
     for (int i = 0; i < n; ++i)
         for (size_t j = 0; j < job_pads[i].size(); ++j) P.jobs[i].s.pad[j] = P.pads[job_pads[i][j]].dst;
@@ -1919,7 +1921,7 @@ ImageKey image_key(const pms_image &im)
 
 size_t pad_bytes_of(const pms_image &im)
 {
-    return align256((size_t)(im.height + 2) * (2 * (size_t)im.width + 4) * pad_elem_size(im.dtype));
+    return align256((size_t)pad_cells(im.width, im.height) * pad_elem_size(im.dtype));
 }
 
 void server_release(pms_server *S, ServerJob *J)
@@ -2142,7 +2144,7 @@ pms_status pms_server_step(pms_server *S, void *stream, int32_t *active_out, int
         for (auto &kv : S->pads)
             if (!kv.second.laid_out) {
                 items.emplace_back((int)P.pads.size(),
-                                   (int)blocks_of((long long)(kv.second.job.H + 2) * kv.second.job.Wp), 0, 0);
+                                   (int)blocks_of(pad_cells(kv.second.job.W, kv.second.job.H)), 0, 0);
                 P.pads.push_back(kv.second.job);
                 kv.second.laid_out = true;
             }

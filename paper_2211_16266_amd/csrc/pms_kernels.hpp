@@ -12,13 +12,14 @@
 //     colour (red-black sweep) or of all pixels (init / cost evaluation); tiles are
 //     handed out so that each XCD walks a contiguous band of rows and keeps
 //     the matching part of the neighbour images in its own L2.
-//   * Neighbour images are re-laid out once per call: every row is repeated
-//     around the seam to width 2W + 4 (columns -W/2-2 .. 3W/2+1), and the
-//     first and last rows are repeated once more above and below (the
-//     clamped pole taps). Any warped sample then reads its two bilinear rows
-//     as two 8-byte buffer loads at an offset built by one add and one clamp
-//     per axis, with no seam or pole test; buffer loads carry the image size,
-//     so no address can leave the image.
+//   * Neighbour images are re-laid out once per call as bilinear cells (a
+//     corner value and its three differences, 16 bytes): every row is
+//     repeated around the seam to width 2W + 4 (columns -W/2-2 .. 3W/2+1),
+//     and the first and last rows are repeated once more above and below
+//     (the clamped pole taps). Any warped sample then reads its whole 2x2
+//     neighbourhood as one 16-byte buffer load at an offset from its
+//     anchor, with no seam or pole test; the offset is clamped to the
+//     storage, so no address can leave it whatever the inputs.
 //   * Precision split: what is shared by all samples of one (pixel,
 //     hypothesis, view) -- relative pose, plane homography, anchor rotation,
 //     warped centre ray and its latitude offset -- is formed in FP64 (on
@@ -111,7 +112,7 @@ struct SweepArgs {
     ImgRef ref;
     ViewPoseD pose[MAXV];    // relative poses in FP64 (warped centre ray)
     ViewPoseF posef[MAXV];   // the same rounded (homography on offsets)
-    const void *pad[MAXV];  // re-laid-out neighbours, (H + 2) x Wp elements
+    const void *pad[MAXV];  // re-laid-out neighbours, (H + 1) x Wp bilinear cells
     int Wp;                 // their pitch in elements, 2W + 4
     int pad_bytes;          // bytes of one re-laid-out image
     const float2 *tab_row;  // per row (sin phi, cos phi)
@@ -140,17 +141,17 @@ struct Storage;
 template <>
 struct Storage<DT_F32> {
     using ref_t = float;
-    using pad_t = float2;
+    using pad_t = float4;
 };
 template <>
 struct Storage<DT_F16> {
     using ref_t = __half;
-    using pad_t = float2;
+    using pad_t = float4;
 };
 template <>
 struct Storage<DT_U8> {
     using ref_t = uint8_t;
-    using pad_t = float2;
+    using pad_t = float4;
 };
 
 // ---------------------------------------------------------------------------
@@ -204,22 +205,15 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, int b
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, bytes, 0x00020000);
 }
 
-// Re-laid-out neighbour images hold, per position, the value and its
-// difference to the next column, (I(x), I(x+1) - I(x)) as float2, so that a
-// horizontal blend is one FMA. Bilinear sample from the pair of the row at
-// byte offset `off` and of the row below (au, av: fractions along x, y).
-template <typename P>
-__device__ __forceinline__ float bilinear(__amdgpu_buffer_rsrc_t r, int off, int rowb, float au, float av);
-
-template <>
-__device__ __forceinline__ float bilinear<float2>(__amdgpu_buffer_rsrc_t r, int off, int rowb, float au,
-                                                  float av)
+// Bilinear sample from the cell at byte offset `off` of a re-laid-out
+// neighbour image (corner value and its three differences): one 16-byte
+// buffer load and three FMAs (au, av: fractions along x, y).
+__device__ __forceinline__ float bilinear(__amdgpu_buffer_rsrc_t r, int off, float au, float av)
 {
-    const float2 p0 = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
-    const float2 p1 = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off + rowb, 0, 0));
-    const float top = fmaf(au, p0.y, p0.x);
-    const float bot = fmaf(au, p1.y, p1.x);
-    return fmaf(av, bot - top, top);
+    const float4 q = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+    const float top = fmaf(au, q.y, q.x);
+    const float dv = fmaf(au, q.w, q.z);
+    return fmaf(av, dv, top);
 }
 
 __device__ __forceinline__ void bearing(const SweepArgs &A, int x, int y, float b[3])
@@ -228,6 +222,14 @@ __device__ __forceinline__ void bearing(const SweepArgs &A, int x, int y, float 
     b[0] = rw.y * cl.x;
     b[1] = -rw.x;
     b[2] = rw.y * cl.y;
+}
+
+// min(max(x, 0), hi) in one instruction (hi >= 0, the same in every lane).
+__device__ __forceinline__ int clamp0_int(int x, int hi)
+{
+    int r;
+    asm("v_med3_i32 %0, %1, 0, %2" : "=v"(r) : "v"(x), "s"(hi));
+    return r;
 }
 
 // floor(x) as an integer in one instruction (x finite and in int range).
@@ -367,7 +369,7 @@ struct ViewSetup {
     float hzc;           // its horizontal length
     float sdc, cdc;      // sin / cos of (centre latitude - phi0), scaled
     float sp0, cp0;      // sin / cos of the anchor latitude phi0
-    int U0p, V0p;        // anchor pixel in re-laid-out storage
+    int base;            // byte offset of the anchor in the re-laid-out storage
     int short_ok;        // every sample angle is in the short atan range
 };
 
@@ -395,8 +397,12 @@ __device__ __forceinline__ void view_setup(const SweepArgs &A, const Patch<SPL> 
     V0 = V0 < 0 ? 0 : (V0 > A.H - 1 ? A.H - 1 : V0);
     const double2 lam0 = A.tab_col64[U0];  // (sin, cos) of the anchor longitude
     const double2 phi0 = A.tab_row64[V0];  // (sin, cos) of the anchor latitude
-    o.U0p = U0 + (A.W >> 1) + 2;
-    o.V0p = V0 + 1;
+    {
+        // anchor position in the re-laid-out storage ((H + 2) rows of Wp
+        // pairs, the image starting at row 1, column W/2 + 2)
+        const int U0p = U0 + (A.W >> 1) + 2, V0p = V0 + 1;
+        o.base = (V0p * A.Wp + U0p) * (int)sizeof(float4);
+    }
     // centre turned about the vertical by -lam0 (FP64). Its longitude is
     // within half a pixel of lam0, so yr2 > 0 and |yr0| << yr2, and the
     // horizontal length is yr2 + yr0^2 / (2 yr2) to FP64 precision.
@@ -441,7 +447,7 @@ __device__ __forceinline__ void view_setup(const SweepArgs &A, const Patch<SPL> 
 // slot is its thread index), so that every lane of a pixel can read the
 // set-up another lane of the same pixel prepared. Only lanes of one wave
 // exchange data, and a wave's LDS operations complete in order.
-constexpr int SETUP_WORDS = 19;
+constexpr int SETUP_WORDS = 18;
 
 struct SetupLds {
     float w[SETUP_WORDS][BLOCK];
@@ -458,9 +464,8 @@ __device__ __forceinline__ void put_setup(SetupLds &L, int slot, const ViewSetup
     L.w[13][slot] = v.cdc;
     L.w[14][slot] = v.sp0;
     L.w[15][slot] = v.cp0;
-    L.w[16][slot] = __int_as_float(v.U0p);
-    L.w[17][slot] = __int_as_float(v.V0p);
-    L.w[18][slot] = __int_as_float(v.short_ok);
+    L.w[16][slot] = __int_as_float(v.base);
+    L.w[17][slot] = __int_as_float(v.short_ok);
 }
 
 __device__ __forceinline__ void get_setup(const SetupLds &L, int slot, ViewSetup &v)
@@ -474,9 +479,8 @@ __device__ __forceinline__ void get_setup(const SetupLds &L, int slot, ViewSetup
     v.cdc = L.w[13][slot];
     v.sp0 = L.w[14][slot];
     v.cp0 = L.w[15][slot];
-    v.U0p = __float_as_int(L.w[16][slot]);
-    v.V0p = __float_as_int(L.w[17][slot]);
-    v.short_ok = __float_as_int(L.w[18][slot]);
+    v.base = __float_as_int(L.w[16][slot]);
+    v.short_ok = __float_as_int(L.w[17][slot]);
 }
 
 // Aggregated cost of plane (d, n) at the pixel of `pt`: per view, warp every
@@ -519,7 +523,9 @@ __device__ __forceinline__ float evaluate(const SweepArgs &A, const Patch<SPL> &
             for (int j = 0; j < A.n_views; ++j) A.view_out[j][out_index] = 2.0f;
         return 2.0f;
     }
-    const int rowb = A.Wp * (int)sizeof(PT);
+    static_assert(sizeof(PT) == 16, "sample offsets are formed as cell index << 4");
+    // the offset of the last cell
+    const int last = A.pad_bytes - (int)sizeof(PT);
     // the top_k smallest view costs, ascending, as bit patterns: costs are
     // non-negative floats, whose order is that of their bits as unsigned
     unsigned top[MAXK];
@@ -546,7 +552,7 @@ __device__ __forceinline__ float evaluate(const SweepArgs &A, const Patch<SPL> &
             const __amdgpu_buffer_rsrc_t img = make_rsrc(A.pad[j], A.pad_bytes);
             const float y0c = V.y0c, y2c = V.y2c, hzcf = V.hzc, sdc = V.sdc, cdc = V.cdc;
             const float sp0 = V.sp0, cp0 = V.cp0;
-            const int U0p = V.U0p, V0p = V.V0p;
+            const int base = V.base;
             float s[SPL];
             float sum = 0.0f;
             // (the short form is compiled in for up to 9 samples per lane
@@ -572,13 +578,13 @@ __device__ __forceinline__ float evaluate(const SweepArgs &A, const Patch<SPL> &
                     const float ul = dl * A.kx, vl = dp * A.ky;
                     // whole and fractional pixel offsets from the anchor
                     const float au = __builtin_amdgcn_fractf(ul), av = __builtin_amdgcn_fractf(vl);
-                    // |ul| <= W/2 keeps the column inside the repeated storage;
-                    // the latitude stays within the poles, so this clamp only
-                    // guards against rounding
-                    const int xi = U0p + floor_int(ul);
-                    const int yi = min(max(V0p + floor_int(vl), 0), A.H);
-                    const int off = (int)(__umul24((unsigned)yi, (unsigned)A.Wp) + (unsigned)xi) * (int)sizeof(PT);
-                    s[i] = bilinear<PT>(img, off, rowb, au, av);
+                    // |ul| <= W/2 keeps the column inside the repeated storage
+                    // and the latitude stays within the poles, so the cell
+                    // lies inside the storage; the clamp only keeps every
+                    // address there whatever the inputs
+                    const int off = clamp0_int(
+                        (int)((unsigned)(__mul24(floor_int(vl), A.Wp) + floor_int(ul)) << 4) + base, last);
+                    s[i] = bilinear(img, off, au, av);
                     sum += FULL ? s[i] : s[i] * pt.wt[i];
                 }
             } else {
@@ -597,10 +603,9 @@ __device__ __forceinline__ float evaluate(const SweepArgs &A, const Patch<SPL> &
                     const float dp = atan2_full(sd, cd);
                     const float ul = dl * A.kx, vl = dp * A.ky;
                     const float au = __builtin_amdgcn_fractf(ul), av = __builtin_amdgcn_fractf(vl);
-                    const int xi = U0p + floor_int(ul);
-                    const int yi = min(max(V0p + floor_int(vl), 0), A.H);
-                    const int off = (int)(__umul24((unsigned)yi, (unsigned)A.Wp) + (unsigned)xi) * (int)sizeof(PT);
-                    s[i] = bilinear<PT>(img, off, rowb, au, av);
+                    const int off = clamp0_int(
+                        (int)((unsigned)(__mul24(floor_int(vl), A.Wp) + floor_int(ul)) << 4) + base, last);
+                    s[i] = bilinear(img, off, au, av);
                     sum += FULL ? s[i] : s[i] * pt.wt[i];
                 }
             }
@@ -791,10 +796,13 @@ __global__ void k_tables(int W, int H, float2 *row, float2 *col, double2 *row64,
     }
 }
 
-// Re-lays out neighbour images: storage row py holds image row
-// clamp(py - 1, 0, H - 1), storage column px holds image column
-// c = (px - W/2 - 2) mod W as the pair (I(c), I(c + 1 mod W) - I(c)) in
-// FP32 (16-bit values widen exactly; 8-bit ones are scaled to [0, 1]).
+// Re-lays out neighbour images as bilinear cells. Storage row py stands for
+// image row clamp(py - 1, 0, H - 1) (the rows above the first and below
+// the last repeat them: the clamped pole taps), storage column px for image
+// column c = (px - W/2 - 2) mod W. Cell (px, py) holds, with a = I(c, r0),
+// b = I(c + 1, r0), e = I(c, r1), f = I(c + 1, r1) for the rows r0, r1 of
+// storage rows py and py + 1: (a, b - a, e - a, (f - e) - (b - a)) in FP32
+// (16-bit values widen exactly; 8-bit ones are scaled to [0, 1]).
 template <typename TS>
 __device__ __forceinline__ void pad_one(const PadJob &J, long long i)
 {
@@ -803,10 +811,13 @@ __device__ __forceinline__ void pad_one(const PadJob &J, long long i)
     sx = sx < 0 ? sx + J.W : sx;
     sx = sx >= J.W ? sx - J.W : sx;
     const int sx1 = sx + 1 == J.W ? 0 : sx + 1;
-    const int sy = py == 0 ? 0 : (py > J.H ? J.H - 1 : py - 1);
-    const float a = load_px<TS>(J.src, sx, sy);
-    const float b = load_px<TS>(J.src, sx1, sy);
-    static_cast<float2 *>(J.dst)[i] = make_float2(a, b - a);
+    const int r0 = py == 0 ? 0 : py - 1;
+    const int r1 = py >= J.H ? J.H - 1 : py;
+    const float a = load_px<TS>(J.src, sx, r0);
+    const float b = load_px<TS>(J.src, sx1, r0);
+    const float e = load_px<TS>(J.src, sx, r1);
+    const float f = load_px<TS>(J.src, sx1, r1);
+    static_cast<float4 *>(J.dst)[i] = make_float4(a, b - a, e - a, (f - e) - (b - a));
 }
 
 __global__ __launch_bounds__(BLOCK) void k_pad(Launch L)
@@ -816,7 +827,7 @@ __global__ __launch_bounds__(BLOCK) void k_pad(Launch L)
     const Entry &E = *const_view<Entry>(L.entries, e);
     const PadJob &J = *const_view<PadJob>(L.table, E.job);
     const long long i = (long long)local * BLOCK + threadIdx.x;
-    if (i >= (long long)(J.H + 2) * J.Wp) return;
+    if (i >= (long long)(J.H + 1) * J.Wp) return;
     if (J.dtype == DT_F16) pad_one<__half>(J, i);
     else if (J.dtype == DT_U8) pad_one<uint8_t>(J, i);
     else pad_one<float>(J, i);
@@ -1020,11 +1031,12 @@ __device__ __forceinline__ void halfsweep_tile(const SweepArgs &A, int tile, int
         float m0 = fmaf(A.sn[t], 2.0f * u[1] - 1.0f, bn0);
         float m1 = fmaf(A.sn[t], 2.0f * u[2] - 1.0f, bn1);
         float m2 = fmaf(A.sn[t], 2.0f * u[3] - 1.0f, bn2);
-        const float len = sqrtf(m0 * m0 + m1 * m1 + m2 * m2);
-        if (!(len > 0.0f)) continue;
-        m0 /= len;
-        m1 /= len;
-        m2 /= len;
+        const float len2 = m0 * m0 + m1 * m1 + m2 * m2;
+        if (!(len2 > 0.0f)) continue;
+        const float il = __builtin_amdgcn_rsqf(len2);
+        m0 *= il;
+        m1 *= il;
+        m2 *= il;
         if (!(m0 * pt.bp[0] + m1 * pt.bp[1] + m2 * pt.bp[2] < 0.0f)) continue;
         const float c = evaluate<PT, LPP, SPL, FULL, false>(A, pt, dd, m0, m1, m2, lane, 0, bc);
         if (c < bc) {
