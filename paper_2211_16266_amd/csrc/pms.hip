@@ -281,6 +281,7 @@ pms::ViewPoseF relative_pose(const pms_pose &ref, const pms_pose &nbr)
     pms::ViewPoseF out;
     for (int i = 0; i < 9; ++i) out.R[i] = (float)R[i];
     for (int i = 0; i < 3; ++i) out.t[i] = (float)t[i];
+    out.tnorm = (float)(std::sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]) * (1.0 + 1e-6));
     return out;
 }
 
@@ -534,7 +535,10 @@ void fill_sweep_args(pms::SweepArgs &A, const JobSpec &J, const Geometry &g, con
     A.cy = (float)(H / 2.0 - 0.5);
     // chord between bearings r pixels apart in x and y is at most their
     // angular distance, r (2 pi / W) + r (pi / H) = 2r (2 pi / W)
-    A.patch_chord = (float)(2.0 * A.r * (2.0 * PI / W) * 1.001);
+    // |b_q - b_p| <= sqrt(dphi^2 + dlam^2) <= sqrt(2) r (2 pi / W) for the
+    // samples within r pixels of the centre (rows and columns both span
+    // 2 pi / W per pixel)
+    A.patch_chord = (float)(std::sqrt(2.0) * A.r * (2.0 * PI / W) * 1.001);
     A.n_offsets = p->n_offsets;
     for (int k = 0; k < p->n_offsets; ++k) {
         A.off_x[k] = p->offsets[k][0];

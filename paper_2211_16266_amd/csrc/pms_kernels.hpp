@@ -74,6 +74,7 @@ constexpr int DT_F32 = 0, DT_F16 = 1, DT_U8 = 2;
 struct ViewPoseF {
     float R[9];
     float t[3];
+    float tnorm;  // |t|, rounded up
 };
 
 struct ViewPoseD {
@@ -95,7 +96,7 @@ struct SweepArgs {
     float var_floor;
     float dmin, dmax, inv_dmin, inv_dmax;
     float kx, cx, ky, cy;  // u = lam * kx + cx, v = phi * ky + cy
-    float patch_chord;     // bound on |b_q - b_p| over the patch
+    float patch_chord;     // bound on |b_q - b_p| over the patch, with a margin
     int n_offsets;
     int off_x[MAXOFF], off_y[MAXOFF];
     int refine_trials;
@@ -421,7 +422,6 @@ __device__ __forceinline__ void view_setup(const SweepArgs &A, const Patch<SPL> 
     // the homography turned by -lam0, in FP32: it only maps the small
     // offsets of the sample bearings from the centre bearing
     const float mcf = (float)mc;
-    float mf2 = 0.0f;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const float nk = k == 0 ? n0 : k == 1 ? n1 : n2;
@@ -431,13 +431,14 @@ __device__ __forceinline__ void view_setup(const SweepArgs &A, const Patch<SPL> 
         o.h[k] = fmaf(cl0, m0, -sl0 * m2);
         o.h[3 + k] = m1;
         o.h[6 + k] = fmaf(sl0, m0, cl0 * m2);
-        mf2 = fmaf(m0, m0, fmaf(m1, m1, fmaf(m2, m2, mf2)));
     }
-    // Every sample offset e = h (b_q - b_p) satisfies |e| <= |M|_F dmax
-    // (turning keeps the norm). If the centre and that bound keep both
-    // angles of every sample in the short form's range, the short form
-    // equals the general one bit for bit.
-    const float E = __builtin_amdgcn_sqrtf(mf2) * A.patch_chord;
+    // Every sample offset e = h (b_q - b_p) satisfies |e| <= |M|_2 |b_q - b_p|
+    // (turning keeps norms), and the spectral norm of M = (-c) R - t n^T is
+    // at most -c + |t| for a rotation R and a unit n; the patch chord bounds
+    // |b_q - b_p|. If the centre and that bound keep both angles of every
+    // sample in the short form's range, the short form equals the general
+    // one bit for bit.
+    const float E = (mcf + Vf.tnorm) * A.patch_chord;
     const float lon_den = o.y2c - E, lat_den = o.cdc - E;
     o.short_ok = lon_den > 1e-30f && fabsf(o.y0c) + E <= SHORT_RANGE * lon_den && lat_den > 1e-30f &&
                  fabsf(o.sdc) + E <= SHORT_RANGE * lat_den;
