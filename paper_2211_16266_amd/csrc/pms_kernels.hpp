@@ -363,6 +363,8 @@ __device__ __forceinline__ void patch_setup(const SweepArgs &A, int x, int y, in
     }
 }
 
+constexpr int SHORT_LON = 1, SHORT_LAT = 2;
+
 // Everything a (pixel, hypothesis, view) shares between its samples.
 struct ViewSetup {
     float h[9];          // homography turned by -lam0, on bearing offsets
@@ -371,7 +373,8 @@ struct ViewSetup {
     float sdc, cdc;      // sin / cos of (centre latitude - phi0), scaled
     float sp0, cp0;      // sin / cos of the anchor latitude phi0
     int base;            // byte offset of the anchor in the re-laid-out storage
-    int short_ok;        // every sample angle is in the short atan range
+    int short_ok;        // SHORT_LON / SHORT_LAT: every sample's longitude /
+                         // latitude offset is in the short atan range
 };
 
 // Sets up view j for plane (n, c) at the pixel of `pt`; mc = -c.
@@ -411,7 +414,7 @@ __device__ __forceinline__ void view_setup(const SweepArgs &A, const Patch<SPL> 
     const double yr2 = fma(lam0.x, yc[0], lam0.y * yc[2]);
     o.y0c = (float)yr0;
     o.y2c = (float)yr2;
-    const double hzc = yr2 + (double)(0.5f * o.y0c * o.y0c / o.y2c);
+    const double hzc = yr2 + (double)(0.5f * o.y0c * o.y0c * __builtin_amdgcn_rcpf(o.y2c));
     // centre: sin and cos of (latitude - phi0), scaled by the ray length
     o.sdc = (float)fma(-yc[1], phi0.y, -hzc * phi0.x);
     o.cdc = (float)fma(hzc, phi0.y, -yc[1] * phi0.x);
@@ -435,13 +438,14 @@ __device__ __forceinline__ void view_setup(const SweepArgs &A, const Patch<SPL> 
     // Every sample offset e = h (b_q - b_p) satisfies |e| <= |M|_2 |b_q - b_p|
     // (turning keeps norms), and the spectral norm of M = (-c) R - t n^T is
     // at most -c + |t| for a rotation R and a unit n; the patch chord bounds
-    // |b_q - b_p|. If the centre and that bound keep both angles of every
-    // sample in the short form's range, the short form equals the general
-    // one bit for bit.
+    // |b_q - b_p|. Where the centre and that bound keep an angle of every
+    // sample in the short form's range, the short form of that angle equals
+    // the general one bit for bit.
     const float E = (mcf + Vf.tnorm) * A.patch_chord;
     const float lon_den = o.y2c - E, lat_den = o.cdc - E;
-    o.short_ok = lon_den > 1e-30f && fabsf(o.y0c) + E <= SHORT_RANGE * lon_den && lat_den > 1e-30f &&
-                 fabsf(o.sdc) + E <= SHORT_RANGE * lat_den;
+    const bool lon_ok = lon_den > 1e-30f && fabsf(o.y0c) + E <= SHORT_RANGE * lon_den;
+    const bool lat_ok = lat_den > 1e-30f && fabsf(o.sdc) + E <= SHORT_RANGE * lat_den;
+    o.short_ok = (lon_ok ? SHORT_LON : 0) | (lat_ok ? SHORT_LAT : 0);
 }
 
 // Per-lane staging of view set-ups in LDS, one array per field (a lane's
@@ -484,6 +488,48 @@ __device__ __forceinline__ void get_setup(const SetupLds &L, int slot, ViewSetup
     v.short_ok = __float_as_int(L.w[17][slot]);
 }
 
+// Warps the lane's samples into one view and bilinear-samples it: s[i] and
+// their (masked) sum. LON / LAT select the short atan form for the
+// longitude / latitude offset from the anchor; callers take a short form
+// only where it equals the general one bit for bit.
+template <bool LON, bool LAT, int SPL, bool FULL>
+__device__ __forceinline__ float warp_samples(const SweepArgs &A, const Patch<SPL> &pt, const ViewSetup &V,
+                                              __amdgpu_buffer_rsrc_t img, int last, float s[SPL])
+{
+    const float y0c = V.y0c, y2c = V.y2c, hzcf = V.hzc, sdc = V.sdc, cdc = V.cdc;
+    const float sp0 = V.sp0, cp0 = V.cp0;
+    float sum = 0.0f;
+#pragma unroll
+    for (int i = 0; i < SPL; ++i) {
+        const float bx = pt.b[i][0], by = pt.b[i][1], bz = pt.b[i][2];
+        // the turned homography on the offset from the centre bearing
+        const float e0 = fmaf(V.h[0], bx, fmaf(V.h[1], by, V.h[2] * bz));
+        const float e1 = fmaf(V.h[3], bx, fmaf(V.h[4], by, V.h[5] * bz));
+        const float e2 = fmaf(V.h[6], bx, fmaf(V.h[7], by, V.h[8] * bz));
+        const float y0 = y0c + e0, y2 = y2c + e2;
+        const float hz = __builtin_amdgcn_sqrtf(fmaf(y0, y0, y2 * y2));
+        // hz - hzc without cancellation
+        const float dhz = fmaf(e0, y0 + y0c, e2 * (y2 + y2c)) * __builtin_amdgcn_rcpf(hz + hzcf);
+        const float sd = fmaf(-dhz, sp0, fmaf(-e1, cp0, sdc));
+        const float cd = fmaf(dhz, cp0, fmaf(-e1, sp0, cdc));
+        // longitude - lam0 and latitude - phi0
+        const float dl = LON ? atan_core(y0 * __builtin_amdgcn_rcpf(y2)) : atan2_full(y0, y2);
+        const float dp = LAT ? atan_core(sd * __builtin_amdgcn_rcpf(cd)) : atan2_full(sd, cd);
+        const float ul = dl * A.kx, vl = dp * A.ky;
+        // whole and fractional pixel offsets from the anchor
+        const float au = __builtin_amdgcn_fractf(ul), av = __builtin_amdgcn_fractf(vl);
+        // |ul| <= W/2 keeps the column inside the repeated storage and the
+        // latitude stays within the poles, so the cell lies inside the
+        // storage; the clamp only keeps every address there whatever the
+        // inputs
+        const int off =
+            clamp0_int((int)((unsigned)(__mul24(floor_int(vl), A.Wp) + floor_int(ul)) << 4) + V.base, last);
+        s[i] = bilinear(img, off, au, av);
+        sum += FULL ? s[i] : s[i] * pt.wt[i];
+    }
+    return sum;
+}
+
 // Aggregated cost of plane (d, n) at the pixel of `pt`: per view, warp every
 // sample, bilinear-sample the neighbour, two-pass NCC, cost = 1 - NCC or 2
 // when invalid; then the mean of the top_k smallest view costs. All lanes of
@@ -512,11 +558,17 @@ __device__ __forceinline__ float evaluate(const SweepArgs &A, const Patch<SPL> &
     const double c64 = (double)d * nbp;
     const float nbpf = (float)nbp;
     int ok = c64 < 0.0;
+    // |n . (b_q - b_p)| <= |b_q - b_p| <= patch_chord (which carries a
+    // margin far above the rounding of den), so a plane with n . b_p below
+    // -patch_chord faces every sample ray; the per-sample test below then
+    // finds the same
+    if (!__all(nbpf < -A.patch_chord)) {
 #pragma unroll
-    for (int i = 0; i < SPL; ++i) {
-        // n . b_q = n . b_p + n . (b_q - b_p)
-        const float den = fmaf(n0, pt.b[i][0], fmaf(n1, pt.b[i][1], fmaf(n2, pt.b[i][2], nbpf)));
-        ok &= FULL ? (den < 0.0f) : (den < 0.0f || pt.wt[i] == 0.0f);
+        for (int i = 0; i < SPL; ++i) {
+            // n . b_q = n . b_p + n . (b_q - b_p)
+            const float den = fmaf(n0, pt.b[i][0], fmaf(n1, pt.b[i][1], fmaf(n2, pt.b[i][2], nbpf)));
+            ok &= FULL ? (den < 0.0f) : (den < 0.0f || pt.wt[i] == 0.0f);
+        }
     }
     ok = group_and<LPP>(ok);
     if (!ok) {
@@ -551,64 +603,18 @@ __device__ __forceinline__ float evaluate(const SweepArgs &A, const Patch<SPL> &
             ViewSetup V;
             get_setup(setup_lds, slot0 + t, V);
             const __amdgpu_buffer_rsrc_t img = make_rsrc(A.pad[j], A.pad_bytes);
-            const float y0c = V.y0c, y2c = V.y2c, hzcf = V.hzc, sdc = V.sdc, cdc = V.cdc;
-            const float sp0 = V.sp0, cp0 = V.cp0;
-            const int base = V.base;
             float s[SPL];
-            float sum = 0.0f;
-            // (the short form is compiled in for up to 9 samples per lane
-            // only: the larger variants cannot hold both copies at their
-            // occupancy)
-            if (SPL <= 9 && __all(V.short_ok)) {
-#pragma unroll
-                for (int i = 0; i < SPL; ++i) {
-                    const float bx = pt.b[i][0], by = pt.b[i][1], bz = pt.b[i][2];
-                    // the turned homography on the offset from the centre bearing
-                    const float e0 = fmaf(V.h[0], bx, fmaf(V.h[1], by, V.h[2] * bz));
-                    const float e1 = fmaf(V.h[3], bx, fmaf(V.h[4], by, V.h[5] * bz));
-                    const float e2 = fmaf(V.h[6], bx, fmaf(V.h[7], by, V.h[8] * bz));
-                    const float y0 = y0c + e0, y2 = y2c + e2;
-                    const float hz = __builtin_amdgcn_sqrtf(fmaf(y0, y0, y2 * y2));
-                    // hz - hzc without cancellation
-                    const float dhz = fmaf(e0, y0 + y0c, e2 * (y2 + y2c)) * __builtin_amdgcn_rcpf(hz + hzcf);
-                    const float sd = fmaf(-dhz, sp0, fmaf(-e1, cp0, sdc));
-                    const float cd = fmaf(dhz, cp0, fmaf(-e1, sp0, cdc));
-                    // longitude - lam0 and latitude - phi0
-                    const float dl = atan_core(y0 * __builtin_amdgcn_rcpf(y2));
-                    const float dp = atan_core(sd * __builtin_amdgcn_rcpf(cd));
-                    const float ul = dl * A.kx, vl = dp * A.ky;
-                    // whole and fractional pixel offsets from the anchor
-                    const float au = __builtin_amdgcn_fractf(ul), av = __builtin_amdgcn_fractf(vl);
-                    // |ul| <= W/2 keeps the column inside the repeated storage
-                    // and the latitude stays within the poles, so the cell
-                    // lies inside the storage; the clamp only keeps every
-                    // address there whatever the inputs
-                    const int off = clamp0_int(
-                        (int)((unsigned)(__mul24(floor_int(vl), A.Wp) + floor_int(ul)) << 4) + base, last);
-                    s[i] = bilinear(img, off, au, av);
-                    sum += FULL ? s[i] : s[i] * pt.wt[i];
-                }
+            float sum;
+            // (the short forms are compiled in for up to 9 samples per lane
+            // only: the larger variants cannot hold more than one copy at
+            // their occupancy)
+            if (SPL <= 9 && __all(V.short_ok & SHORT_LAT)) {
+                if (__all(V.short_ok & SHORT_LON))
+                    sum = warp_samples<true, true, SPL, FULL>(A, pt, V, img, last, s);
+                else
+                    sum = warp_samples<false, true, SPL, FULL>(A, pt, V, img, last, s);
             } else {
-#pragma unroll
-                for (int i = 0; i < SPL; ++i) {
-                    const float bx = pt.b[i][0], by = pt.b[i][1], bz = pt.b[i][2];
-                    const float e0 = fmaf(V.h[0], bx, fmaf(V.h[1], by, V.h[2] * bz));
-                    const float e1 = fmaf(V.h[3], bx, fmaf(V.h[4], by, V.h[5] * bz));
-                    const float e2 = fmaf(V.h[6], bx, fmaf(V.h[7], by, V.h[8] * bz));
-                    const float y0 = y0c + e0, y2 = y2c + e2;
-                    const float hz = __builtin_amdgcn_sqrtf(fmaf(y0, y0, y2 * y2));
-                    const float dhz = fmaf(e0, y0 + y0c, e2 * (y2 + y2c)) * __builtin_amdgcn_rcpf(hz + hzcf);
-                    const float sd = fmaf(-dhz, sp0, fmaf(-e1, cp0, sdc));
-                    const float cd = fmaf(dhz, cp0, fmaf(-e1, sp0, cdc));
-                    const float dl = atan2_full(y0, y2);
-                    const float dp = atan2_full(sd, cd);
-                    const float ul = dl * A.kx, vl = dp * A.ky;
-                    const float au = __builtin_amdgcn_fractf(ul), av = __builtin_amdgcn_fractf(vl);
-                    const int off = clamp0_int(
-                        (int)((unsigned)(__mul24(floor_int(vl), A.Wp) + floor_int(ul)) << 4) + base, last);
-                    s[i] = bilinear(img, off, au, av);
-                    sum += FULL ? s[i] : s[i] * pt.wt[i];
-                }
+                sum = warp_samples<false, false, SPL, FULL>(A, pt, V, img, last, s);
             }
             sum = group_sum<LPP>(sum);
             const float ms = sum * A.inv_P;
