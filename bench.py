@@ -57,12 +57,15 @@ METRIC = "keyframes/s + p50/p99 latency @1920×960, 4 nbrs; NCC evals/s vs roofl
 SLOTS_PER_SAMPLE = 76
 SLOTS_PER_EVAL = 30
 # The same unit priced by the gfx950 ISA of this build's short-form sample
-# loop (about 56 VALU instructions a sample, its 3 rcp and 1 sqrt issuing at
-# half rate) and per evaluation (NCC finish, top-k, the shared view set-up
-# and its LDS exchange): an estimate of the VALU utilisation, not the
-# contract figure above.
-ISA_SLOTS_PER_SAMPLE = 60
-ISA_SLOTS_PER_EVAL = 150
+# loop (about 49 VALU instructions a sample, its 3 rcp and 1 sqrt issuing at
+# half rate: 52 slots) and per evaluation (the NCC finish, top-k insertion
+# and LDS read of the view set-up, about 87 slots, plus a quarter of the
+# FP64 view set-up and candidate handling that four views share, about 78):
+# an estimate of the VALU utilisation, not the contract figure above. The
+# contract figure is an estimate too (+-25%); since this build's sample loop
+# needs fewer slots than it, the contract fraction can exceed 1.
+ISA_SLOTS_PER_SAMPLE = 52
+ISA_SLOTS_PER_EVAL = 165
 PEAK_TSLOTS = 256 * 64 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 # algorithmic HBM bytes per updated pixel of a half-sweep: own plane 16 +
@@ -669,6 +672,8 @@ def main() -> int:
             "launches": n_half,
             "algorithmic_per_launch": {"ncc_evals": evals_per_launch, "slots": slots_per_launch,
                                        "hbm_bytes": hbm_bytes},
+            "pricing": {"slots_per_sample": SLOTS_PER_SAMPLE, "slots_per_eval": SLOTS_PER_EVAL,
+                        "isa_slots_per_sample": ISA_SLOTS_PER_SAMPLE, "isa_slots_per_eval": ISA_SLOTS_PER_EVAL},
             "isa_priced_frac": evals_per_launch * (P * ISA_SLOTS_PER_SAMPLE + ISA_SLOTS_PER_EVAL)
                                / avg_half_s / 1e12 / PEAK_TSLOTS,
             "hbm_achieved_GBs": hbm_bytes / avg_half_s / 1e9,
