@@ -912,12 +912,15 @@ __device__ __forceinline__ void init_tile(const SweepArgs &A, int tile)
     float sa, ca;
     sincosf(a, &sa, &ca);
     float n0 = s * ca, n1 = s * sa, n2 = z;
-    const float nb = n0 * pt.bp[0] + n1 * pt.bp[1] + n2 * pt.bp[2];
-    if (nb > 0.0f) {
+    // the side is decided in FP64 with the FP64 bearing, as every later
+    // test of a plane facing the camera is (negation is exact, so the
+    // flipped normal faces it in FP64 too)
+    const double nb = (double)n0 * pt.bp64[0] + (double)n1 * pt.bp64[1] + (double)n2 * pt.bp64[2];
+    if (nb > 0.0) {
         n0 = -n0;
         n1 = -n1;
         n2 = -n2;
-    } else if (nb == 0.0f) {
+    } else if (nb == 0.0) {
         n0 = -pt.bp[0];
         n1 = -pt.bp[1];
         n2 = -pt.bp[2];

@@ -192,3 +192,55 @@ def test_autotune_picks_a_shape_and_keeps_results(pms):
     for k, jd in enumerate(jobs):
         assert _same(jd.out, ref[k])
     ctx.close()
+
+
+def test_full_size_mixed_batch_sampled(pms):
+    """One job of each size class of the 32-job mix (960x480, 1920x960 and
+    2880x1440 hall windows, FP16 images, 3-6 neighbours), run as one batch
+    replayed from a HIP graph, as the benchmark runs the mix: every job
+    equals its solo run bit for bit, and at sampled pixels the stored cost
+    is the oracle's cost of the stored plane on the same (FP16-rounded)
+    intensities; every job finds most of the ground truth."""
+    from helpers import bearings
+    pool = synth.mixed_pool(seed=0, dtype="f16")
+    mix = synth.mixed_jobs({960: 1, 1920: 1, 2880: 1}, seed=5)
+    dev = {W: [torch.from_numpy(a).cuda() for a in w.images] for W, w in pool.items()}
+    jobs = []
+    for mj in mix:
+        w = pool[mj.W]
+        jobs.append(pms.job(dev[mj.W][mj.ref], [dev[mj.W][k] for k in mj.nbrs], w.poses[mj.ref],
+                            [w.poses[k] for k in mj.nbrs], dict(w.params, seed=mj.seed)))
+    ctx = pms.Context(0)
+    batch = pms.Batch(jobs, ctx=ctx)
+    say(f"graph batch of {len(jobs)} full-size FP16 jobs")
+    batch.run(graph=True)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(12)
+    for mj, jd in zip(mix, jobs):
+        w = pool[mj.W]
+        say(f"solo run of the {mj.W}x{mj.W // 2} job, {len(mj.nbrs)} neighbours")
+        solo = _alone(pms, jd, ctx)
+        torch.cuda.synchronize()
+        assert _same(jd.out, solo), f"{mj.W}: batch differs from the solo run"
+        d, n, c = (t.cpu().numpy() for t in jd.out)
+        params = jd.params
+        r = (params["patch_size"] - 1) // 2
+        ref64 = w.images[mj.ref].astype(np.float64)
+        nb64 = [w.images[k].astype(np.float64) for k in mj.nbrs]
+        R = [oracle.relative_pose(w.poses[mj.ref], w.poses[k]) for k in mj.nbrs]
+        for _ in range(60):
+            y, x = int(rng.integers(r, w.H - r)), int(rng.integers(0, w.W))
+            vc = [oracle.view_cost(ref64, nb, Rj, tj, params, x, y, float(d[y, x]),
+                                   n[:, y, x].astype(np.float64))[0] for nb, (Rj, tj) in zip(nb64, R)]
+            co = oracle.aggregate(vc, params["top_k"])
+            assert abs(co - c[y, x]) <= 1e-4 or min(vc) >= 2.0 and c[y, x] == 2.0, (mj.W, x, y, co, c[y, x])
+        band = np.zeros_like(d, dtype=bool)
+        band[r:w.H - r] = True
+        assert np.all((n * bearings(w.W, w.H)).sum(0)[band] < 0)
+        gt = w.gt_depth[mj.ref]
+        rel = np.abs(d - gt) / np.maximum(gt, 1e-6)
+        within = (rel[band & (gt > 0)] < 0.01).mean()
+        print(f"{mj.W}: {within:.3f} of pixels within 1% of ground truth")
+        assert within > 0.5
+    batch.close()
+    ctx.close()
