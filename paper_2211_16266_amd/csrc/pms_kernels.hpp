@@ -257,6 +257,18 @@ __device__ __forceinline__ float atan_core(float t)
     return fmaf(t * s, p, t);
 }
 
+// G(u) = 1 / (1 + sqrt(1 + u)) for u in [0, tan^2(pi/8)], so that
+// y2 sqrt(1 + tau^2) = y2 + y2 u G(u) with u = tau^2: degree 4, fitted for
+// minimum relative error (8e-9 in exact arithmetic, 5e-8 evaluated in FP32;
+// hz_coeffs.py).
+__device__ __forceinline__ float hz_core(float u)
+{
+    float p = fmaf(u, 2.019176260e-02f, -3.806483746e-02f);
+    p = fmaf(p, u, 6.244114041e-02f);
+    p = fmaf(p, u, -1.249987707e-01f);
+    return fmaf(p, u, 0.5f);
+}
+
 // atan2 for any arguments (both zero give 0): octant reduction to t in
 // [0, 1], then t > tan(pi/8) is mapped to (t - 1) / (t + 1) in (-tan(pi/8), 0]
 // with atan t = pi/4 + atan((t - 1) / (t + 1)).
@@ -369,7 +381,7 @@ constexpr int SHORT_LON = 1, SHORT_LAT = 2;
 struct ViewSetup {
     float h[9];          // homography turned by -lam0, on bearing offsets
     float y0c, y2c;      // turned warped centre ray, x and z
-    float hzc;           // its horizontal length
+    float kc;            // its horizontal length minus y2c
     float sdc, cdc;      // sin / cos of (centre latitude - phi0), scaled
     float sp0, cp0;      // sin / cos of the anchor latitude phi0
     int base;            // byte offset of the anchor in the re-laid-out storage
@@ -418,7 +430,7 @@ __device__ __forceinline__ void view_setup(const SweepArgs &A, const Patch<SPL> 
     // centre: sin and cos of (latitude - phi0), scaled by the ray length
     o.sdc = (float)fma(-yc[1], phi0.y, -hzc * phi0.x);
     o.cdc = (float)fma(hzc, phi0.y, -yc[1] * phi0.x);
-    o.hzc = (float)hzc;
+    o.kc = (float)(hzc - yr2);
     o.sp0 = (float)phi0.x;
     o.cp0 = (float)phi0.y;
     const float sl0 = (float)lam0.x, cl0 = (float)lam0.y;
@@ -464,7 +476,7 @@ __device__ __forceinline__ void put_setup(SetupLds &L, int slot, const ViewSetup
     for (int k = 0; k < 9; ++k) L.w[k][slot] = v.h[k];
     L.w[9][slot] = v.y0c;
     L.w[10][slot] = v.y2c;
-    L.w[11][slot] = v.hzc;
+    L.w[11][slot] = v.kc;
     L.w[12][slot] = v.sdc;
     L.w[13][slot] = v.cdc;
     L.w[14][slot] = v.sp0;
@@ -479,7 +491,7 @@ __device__ __forceinline__ void get_setup(const SetupLds &L, int slot, ViewSetup
     for (int k = 0; k < 9; ++k) v.h[k] = L.w[k][slot];
     v.y0c = L.w[9][slot];
     v.y2c = L.w[10][slot];
-    v.hzc = L.w[11][slot];
+    v.kc = L.w[11][slot];
     v.sdc = L.w[12][slot];
     v.cdc = L.w[13][slot];
     v.sp0 = L.w[14][slot];
@@ -496,7 +508,7 @@ template <bool LON, bool LAT, int SPL, bool FULL>
 __device__ __forceinline__ float warp_samples(const SweepArgs &A, const Patch<SPL> &pt, const ViewSetup &V,
                                               __amdgpu_buffer_rsrc_t img, int last, float s[SPL])
 {
-    const float y0c = V.y0c, y2c = V.y2c, hzcf = V.hzc, sdc = V.sdc, cdc = V.cdc;
+    const float y0c = V.y0c, y2c = V.y2c, kc = V.kc, sdc = V.sdc, cdc = V.cdc;
     const float sp0 = V.sp0, cp0 = V.cp0;
     float sum = 0.0f;
 #pragma unroll
@@ -507,13 +519,22 @@ __device__ __forceinline__ float warp_samples(const SweepArgs &A, const Patch<SP
         const float e1 = fmaf(V.h[3], bx, fmaf(V.h[4], by, V.h[5] * bz));
         const float e2 = fmaf(V.h[6], bx, fmaf(V.h[7], by, V.h[8] * bz));
         const float y0 = y0c + e0, y2 = y2c + e2;
-        const float hz = __builtin_amdgcn_sqrtf(fmaf(y0, y0, y2 * y2));
-        // hz - hzc without cancellation
-        const float dhz = fmaf(e0, y0 + y0c, e2 * (y2 + y2c)) * __builtin_amdgcn_rcpf(hz + hzcf);
+        // tangent of the longitude offset, and hz - hzc without cancellation:
+        // with u = tau^2, hz = y2 + y2 u G(u) and hzc = y2c + kc, so
+        // hz - hzc = (e2 - kc) + y2 u G(u) while |tau| <= tan(pi/8) (always
+        // in the short form; the general form takes the same expression
+        // there, so both agree bit for bit). Beyond that the sample lies
+        // over 22 degrees of longitude from the anchor (a grazing warp) and
+        // the plain difference of the lengths is accurate enough.
+        const float tau = y0 * __builtin_amdgcn_rcpf(y2);
+        const float u = tau * tau;
+        float dhz = fmaf(y2 * u, hz_core(u), e2 - kc);
+        if (!LON && !(y2 > 0.0f && fabsf(tau) <= TAN_PI_8))
+            dhz = __builtin_amdgcn_sqrtf(fmaf(y0, y0, y2 * y2)) - (y2c + kc);
         const float sd = fmaf(-dhz, sp0, fmaf(-e1, cp0, sdc));
         const float cd = fmaf(dhz, cp0, fmaf(-e1, sp0, cdc));
         // longitude - lam0 and latitude - phi0
-        const float dl = LON ? atan_core(y0 * __builtin_amdgcn_rcpf(y2)) : atan2_full(y0, y2);
+        const float dl = LON ? atan_core(tau) : atan2_full(y0, y2);
         const float dp = LAT ? atan_core(sd * __builtin_amdgcn_rcpf(cd)) : atan2_full(sd, cd);
         const float ul = dl * A.kx, vl = dp * A.ky;
         // whole and fractional pixel offsets from the anchor
