@@ -57,8 +57,8 @@ METRIC = "keyframes/s + p50/p99 latency @1920×960, 4 nbrs; NCC evals/s vs roofl
 SLOTS_PER_SAMPLE = 76
 SLOTS_PER_EVAL = 30
 # The same unit priced by the gfx950 ISA of this build's short-form sample
-# loop (about 49 VALU instructions a sample, its 3 rcp and 1 sqrt issuing at
-# half rate: 52 slots) and per evaluation (the NCC finish, top-k insertion
+# loop (about 50 VALU instructions a sample, its 2 rcp issuing at half
+# rate: 52 slots) and per evaluation (the NCC finish, top-k insertion
 # and LDS read of the view set-up, about 87 slots, plus a quarter of the
 # FP64 view set-up and candidate handling that four views share, about 78):
 # an estimate of the VALU utilisation, not the contract figure above. The
