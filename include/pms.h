@@ -71,7 +71,7 @@ typedef enum { PMS_F32 = 0, PMS_F16 = 1, PMS_U8 = 2 } pms_dtype;
 #define PMS_MAX_TRIALS 16    /* refinement trials per pixel and sweep      */
 #define PMS_MAX_BATCH 256    /* jobs per batch                             */
 #define PMS_MAX_TOP_K 4      /* views averaged (top_k, or ceil(N/2))       */
-#define PMS_MAX_HEIGHT 5790  /* image rows: a neighbour's re-laid-out copy,
+#define PMS_MAX_HEIGHT 5791  /* image rows: a neighbour's re-laid-out copy,
                                 (H + 1) x (2W + 4) cells of 16 bytes, stays
                                 under 2 GiB (32-bit byte offsets)          */
 

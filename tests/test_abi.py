@@ -133,6 +133,18 @@ def test_malformed_calls_are_rejected_before_launch(B, vctx, mutate, expect):
     assert B.lib().pms_last_error(vctx) != b""
 
 
+def test_image_height_limit(B, vctx):
+    """A re-laid-out neighbour copy must stay under 2 GiB of 32-bit byte
+    offsets: the largest accepted height is PMS_MAX_HEIGHT."""
+    hdr = open(HEADER).read()
+    hmax = int(re.search(r"#define PMS_MAX_HEIGHT\s+(\d+)", hdr).group(1))
+    # (H + 1) rows of 2W + 4 cells of 16 bytes, W = 2H
+    assert (hmax + 1) * (4 * hmax + 4) * 16 < 2 ** 31 <= (hmax + 2) * (4 * hmax + 8) * 16
+    assert _Call(B, W=2 * hmax).densify(vctx) == DEVICE
+    assert _Call(B, W=2 * (hmax + 1)).densify(vctx) == INVALID
+    assert b"PMS_MAX_HEIGHT" in B.lib().pms_last_error(vctx)
+
+
 def test_other_entry_points_validate(B, vctx):
     L = B.lib()
     c = _Call(B)
