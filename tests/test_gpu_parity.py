@@ -207,6 +207,47 @@ def test_halfsweep_matches_oracle_update(pms, name, colour):
     assert frac >= 0.99
 
 
+@pytest.mark.parametrize("variant", ["top1", "top3", "top4", "eight_views"])
+def test_aggregation_variants_match_oracle(pms, variant):
+    """Other aggregations: top_k = 1, 3 and 4 of the four views (the pruning
+    bound then applies after other numbers of views), and eight views (the
+    four neighbours twice: two full rounds of shared view set-ups, top_k 4).
+    Per-view and aggregated costs on random hypotheses, then one half-sweep
+    from an oracle-scored state at sampled pixels."""
+    w = _workload("hall384")
+    if variant == "eight_views":
+        w.nbrs = list(w.nbrs) * 2
+    else:
+        w.params = dict(w.params, top_k=int(variant[3:]))
+    params = dict(w.params)
+    d, n = random_hypotheses(w, seed=51)
+    imgs = gpu_images(w)
+    ref, nbrs = split(w, imgs)
+    rp, nps = _poses(w)
+    say(f"eval_cost hall384 {variant}")
+    cost_g, pv_g = pms.eval_cost(ref, nbrs, rp, nps, params, _t(d), _t(n), per_view=True)
+    torch.cuda.synchronize()
+    cost_g = cost_g.cpu().numpy().astype(np.float64)
+    pv_g = pv_g.cpu().numpy().astype(np.float64)
+    imgs64 = _oracle_view_images(w)
+    r64, n64 = split(w, imgs64)
+    cost_o, pv_o = oracle.eval_cost(r64, n64, rp, nps, params, d.astype(np.float64),
+                                    n.astype(np.float64))
+    _compare_view_costs(w, imgs64, d, n, pv_g, pv_o, params)
+    agg_ok = (np.abs(cost_g - cost_o) <= 1e-4) | ((pv_g < 2) != (pv_o < 2)).any(0)
+    assert agg_ok.mean() >= 0.998
+    dd, nn, cc = _state_from_oracle(w, seed=53)
+    r = (params["patch_size"] - 1) // 2
+    rng = np.random.default_rng(6)
+    ys = rng.integers(r, w.H - r, 600)
+    xs = rng.integers(0, w.W // 2, 600) * 2 + (ys & 1)  # colour 0: x + y even
+    pix = sorted({(int(y), int(x)) for y, x in zip(ys, xs)})
+    say(f"halfsweep hall384 {variant} colour=0 {len(pix)} sampled pixels")
+    frac = _check_halfsweep(pms, w, dd, nn, cc, 0, 2, pix)
+    print(f"hall384 {variant}: identical choice at {frac:.4f}")
+    assert frac >= 0.99
+
+
 def _e2e(pms, w, params, maps=False):
     imgs = gpu_images(w)
     ref, nbrs = split(w, imgs)
