@@ -548,7 +548,8 @@ void fill_sweep_args(pms::SweepArgs &A, const JobSpec &J, const Geometry &g, con
     const double sd0 = p->refine_sigma_logdepth0 > 0.0 ? p->refine_sigma_logdepth0
                                                        : 0.5 * std::log(p->depth_max / p->depth_min);
     for (int k = 0; k < p->refine_trials; ++k) {
-        A.sd[k] = (float)(sd0 * std::pow(p->refine_depth_shrink, k));
+        // (in log2 units: the kernel scales the depth by a power of two)
+        A.sd[k] = (float)(sd0 * std::pow(p->refine_depth_shrink, k) / std::log(2.0));
         A.sn[k] = (float)(p->refine_sigma_normal0 * std::pow(p->refine_normal_shrink, k));
     }
     A.seed = p->seed;

@@ -100,7 +100,7 @@ struct SweepArgs {
     int n_offsets;
     int off_x[MAXOFF], off_y[MAXOFF];
     int refine_trials;
-    float sd[MAXTRIAL], sn[MAXTRIAL];
+    float sd[MAXTRIAL], sn[MAXTRIAL];  // per trial: log2-depth and normal spread
     unsigned long long seed;
     // tile shape: a wave covers (1 << wx_log2) x ((64 / LPP) >> wx_log2)
     // pixels, a workgroup (1 << bx_log2) x (4 >> bx_log2) waves
@@ -1010,7 +1010,7 @@ __device__ __forceinline__ void halfsweep_tile(const SweepArgs &A, int tile, int
         const float cq = sq.w * (sq.x * bq[0] + sq.y * bq[1] + sq.z * bq[2]);
         const float den = sq.x * pt.bp[0] + sq.y * pt.bp[1] + sq.z * pt.bp[2];
         if (!(den < 0.0f)) continue;
-        const float dd = cq / den;
+        const float dd = cq * __builtin_amdgcn_rcpf(den);
         if (!(dd >= A.dmin && dd <= A.dmax)) continue;
         // (the stored cost of the current plane is this evaluation's result
         // only when these kernels computed it)
@@ -1057,7 +1057,9 @@ __device__ __forceinline__ void halfsweep_tile(const SweepArgs &A, int tile, int
         }
         const float4 uv = draws_lds[slot0 + j];
         const float u[4] = {uv.x, uv.y, uv.z, uv.w};
-        float dd = bd * expf((2.0f * u[0] - 1.0f) * A.sd[t]);
+        // depth x e^((2u - 1) sigma) as a power of two (|exponent| stays far
+        // inside the range where v_exp_f32 is exact to an ulp)
+        float dd = bd * __builtin_amdgcn_exp2f((2.0f * u[0] - 1.0f) * A.sd[t]);
         dd = fminf(fmaxf(dd, A.dmin), A.dmax);
         float m0 = fmaf(A.sn[t], 2.0f * u[1] - 1.0f, bn0);
         float m1 = fmaf(A.sn[t], 2.0f * u[2] - 1.0f, bn1);
