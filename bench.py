@@ -96,19 +96,20 @@ def measured_traffic(schedule: dict):
     summary (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads
     for a plain copy of known size), or None when the summary is missing or
     was taken on other kernel sources."""
+    want = [schedule["wave_rows"], schedule["waves_x"]]
+    for rec in _traffic_records():
+        if rec.get("kernel_sources") == kernel_source_hash() and rec.get("schedule") == want:
+            return rec
+    return None
+
+
+def _traffic_records() -> list:
     path = os.path.join(ROOT, COUNTER_SUMMARY)
     if not os.path.exists(path):
-        return None
-    rec = None
+        return []
     with open(path) as f:
-        for line in f:
-            if line.startswith("<!-- traffic "):
-                rec = json.loads(line[len("<!-- traffic "):].rsplit("-->", 1)[0])
-    if not rec or rec.get("kernel_sources") != kernel_source_hash():
-        return None
-    if rec.get("schedule") != [schedule["wave_rows"], schedule["waves_x"]]:
-        return None
-    return rec
+        return [json.loads(line[len("<!-- traffic "):].rsplit("-->", 1)[0])
+                for line in f if line.startswith("<!-- traffic ")]
 
 
 def valid_pixels(W: int, H: int, params: dict) -> int:
@@ -468,11 +469,8 @@ def counter_summary(fetch_dir: str, write_dir: str, probe_bytes: int, commands: 
            "write_kib_raw": out["WRITE_SIZE"]["halfsweep_kib"],
            "fetch_scale": out["FETCH_SIZE"]["scale"], "write_scale": out["WRITE_SIZE"]["scale"],
            "dispatches": out["FETCH_SIZE"]["dispatches"]}
-    lines = [
-        "# HBM traffic of the half-sweep kernel, hall_1920 (1920x960, 4 neighbours, 36-sample patch)",
-        "",
-        "Two rocprofv3 counter runs of the benchmark with a 256 MiB device copy run",
-        "once before the timed steps (the probe calibrates each counter):",
+    block = [
+        f"## Tile shape {schedule[0]},{schedule[1]}",
         "",
         *[f"    {c}" for c in commands],
         "",
@@ -484,16 +482,34 @@ def counter_summary(fetch_dir: str, write_dir: str, probe_bytes: int, commands: 
         f"{probe_bytes / 1024:.0f} KiB | {rec['write_scale']:.3f} | {write / 1e6:.1f} MB |",
         "",
         f"Traffic per half-sweep launch: {(fetch + write) / 1e6:.1f} MB over "
-        f"{rec['dispatches']} dispatches; kernel sources {rec['kernel_sources']}, tile shape "
-        f"{schedule[0]},{schedule[1]} (the benchmark reports this figure only for the same sources "
-        "and shape).",
+        f"{rec['dispatches']} dispatches; kernel sources {rec['kernel_sources']}.",
         "",
         "<!-- traffic " + json.dumps(rec) + " -->",
         "",
     ]
+    # keep the other tile shapes measured on the same kernel sources
     path = os.path.join(ROOT, COUNTER_SUMMARY)
+    blocks = {tuple(schedule): block}
+    if os.path.exists(path):
+        text = open(path).read()
+        for part in text.split("\n## Tile shape ")[1:]:
+            lines = ("## Tile shape " + part).rstrip("\n").split("\n")
+            recs = [json.loads(x[len("<!-- traffic "):].rsplit("-->", 1)[0])
+                    for x in lines if x.startswith("<!-- traffic ")]
+            if recs and recs[0].get("kernel_sources") == rec["kernel_sources"] \
+                    and tuple(recs[0]["schedule"]) != tuple(schedule):
+                blocks[tuple(recs[0]["schedule"])] = lines + [""]
+    head = [
+        "# HBM traffic of the half-sweep kernel, hall_1920 (1920x960, 4 neighbours, 36-sample patch)",
+        "",
+        "Per tile shape, two rocprofv3 counter runs of the benchmark with a 256 MiB",
+        "device copy run once before the timed steps (the probe calibrates each",
+        "counter). The benchmark reports the figure of the shape it runs, and only",
+        "for the same kernel sources.",
+        "",
+    ]
     with open(path, "w") as f:
-        f.write("\n".join(lines))
+        f.write("\n".join(head + [x for k in sorted(blocks) for x in blocks[k]]))
     return path
 
 
