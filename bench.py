@@ -82,12 +82,41 @@ KERNEL_SOURCES = ("paper_2211_16266_amd/csrc/pms_kernels.hpp", "paper_2211_16266
 COUNTER_SUMMARY = "profiles/halfsweep_hall_1920_hbm_counters.md"
 
 
-def kernel_source_hash() -> str:
+def _code_only(src: str) -> str:
+    """C++ source without comments and blank runs (string literals kept)."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        c = src[i]
+        if c == '"':
+            j = i + 1
+            while j < n and src[j] != '"':
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        elif src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+        else:
+            out.append(c)
+            i += 1
+    return "\n".join(line.rstrip() for line in "".join(out).splitlines() if line.strip())
+
+
+def kernel_source_hash(read=None) -> str:
+    """Hash of the kernel sources' code (comments and blank lines left out,
+    so that a comment edit does not void the recorded counters)."""
     import hashlib
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        if read is None:
+            with open(os.path.join(ROOT, rel), encoding="utf-8") as f:
+                text = f.read()
+        else:
+            text = read(rel)
+        h.update(_code_only(text).encode())
     return h.hexdigest()[:16]
 
 

@@ -65,8 +65,8 @@ constexpr int BLOCK = 256;    // threads per workgroup (4 waves)
 // to avoid a couple of spill slots outside the sample loop; the larger
 // variants keep the compiler's choice.
 #define PMS_OCCUPANCY(SPL) __attribute__((amdgpu_waves_per_eu((SPL) <= 9 ? 4 : 1, 8)))
-// Re-laid-out neighbour image: H + 2 rows of 2W + 4 (value, difference) pairs;
-// logical column x is stored at x + W/2 + 2, logical row y at y + 1.
+// Re-laid-out neighbour image: H + 1 rows of 2W + 4 bilinear cells (16
+// bytes); logical column x is stored at x + W/2 + 2, logical row y at y + 1.
 
 // dtype codes of the C ABI
 constexpr int DT_F32 = 0, DT_F16 = 1, DT_U8 = 2;
@@ -414,8 +414,8 @@ __device__ __forceinline__ void view_setup(const SweepArgs &A, const Patch<SPL> 
     const double2 lam0 = A.tab_col64[U0];  // (sin, cos) of the anchor longitude
     const double2 phi0 = A.tab_row64[V0];  // (sin, cos) of the anchor latitude
     {
-        // anchor position in the re-laid-out storage ((H + 2) rows of Wp
-        // pairs, the image starting at row 1, column W/2 + 2)
+        // anchor position in the re-laid-out storage ((H + 1) rows of Wp
+        // cells, the image starting at row 1, column W/2 + 2)
         const int U0p = U0 + (A.W >> 1) + 2, V0p = V0 + 1;
         o.base = (V0p * A.Wp + U0p) * (int)sizeof(float4);
     }
