@@ -389,13 +389,42 @@ struct ViewSetup {
                          // latitude offset is in the short atan range
 };
 
-// Sets up view j for plane (n, c) at the pixel of `pt`; mc = -c.
+// The job's relative poses, staged in LDS once per workgroup: every lane of
+// a pixel sets up another view, so reading them from the argument table
+// would take vector loads per lane and view set-up.
+struct PoseStage {
+    ViewPoseD d[MAXV];
+    ViewPoseF f[MAXV];
+};
+
+__device__ __forceinline__ PoseStage &pose_stage()
+{
+    __shared__ PoseStage stage;
+    return stage;
+}
+
+// Copies the poses of A's views into the stage; every thread of the
+// workgroup calls it (it ends with a workgroup barrier).
+__device__ __forceinline__ void stage_poses(const SweepArgs &A)
+{
+    PoseStage &S = pose_stage();
+    const int nd = A.n_views * (int)(sizeof(ViewPoseD) / sizeof(double));
+    const int nf = A.n_views * (int)(sizeof(ViewPoseF) / sizeof(float));
+    const double *srcd = reinterpret_cast<const double *>(A.pose);
+    const float *srcf = reinterpret_cast<const float *>(A.posef);
+    for (int i = threadIdx.x; i < nd; i += BLOCK) reinterpret_cast<double *>(S.d)[i] = srcd[i];
+    for (int i = threadIdx.x; i < nf; i += BLOCK) reinterpret_cast<float *>(S.f)[i] = srcf[i];
+    __syncthreads();
+}
+
+// Sets up view j for plane (n, c) at the pixel of `pt`; mc = -c. Reads the
+// poses from the workgroup's stage.
 template <int SPL>
 __device__ __forceinline__ void view_setup(const SweepArgs &A, const Patch<SPL> &pt, int j, double mc,
                                            double nbp, float n0, float n1, float n2, ViewSetup &o)
 {
-    const ViewPoseD &V = A.pose[j];
-    const ViewPoseF &Vf = A.posef[j];
+    const ViewPoseD &V = pose_stage().d[j];
+    const ViewPoseF &Vf = pose_stage().f[j];
     // warped centre ray in FP64: M b_p = (-c) R b_p - t (n . b_p), where
     // M = (-c) R - t n^T is a positive multiple of the plane homography
     double yc[3];
@@ -1128,6 +1157,7 @@ __global__ __launch_bounds__(BLOCK) PMS_OCCUPANCY(SPL) void k_tiles(Launch L)
     if (!block_entry(L, e, local)) return;
     const Entry &E = *const_view<Entry>(L.entries, e);
     const SweepArgs &A = const_view<JobArgs>(L.table, E.job)->s;
+    stage_poses(A);
     if (KIND == TK_INIT) init_tile<DT, LPP, SPL, FULL>(A, local);
     else if (KIND == TK_HALFSWEEP) halfsweep_tile<DT, LPP, SPL, FULL>(A, local, E.iteration, E.colour);
     else eval_tile<DT, LPP, SPL, FULL>(A, local);
