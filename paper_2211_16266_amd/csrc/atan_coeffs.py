@@ -6,8 +6,10 @@ on 4001 points; scipy's HiGHS). Larger arguments are reduced to this range
 by the kernels (octant symmetry and atan t = pi/4 + atan((t-1)/(t+1))). The
 kernels mostly call it on local angles (measured from an anchor pixel),
 where relative accuracy keeps the sample coordinates exact to a few 1e-6 px.
-Run this file to print the coefficients (as float32) and the error of the
-float32 evaluation; the kernels hold the printed values.
+A second, cheaper polynomial (fit_anchor) serves the choice of the anchor
+pixel, which needs the angle only to a fraction of a pixel. Run this file
+to print the coefficients (as float32) and the errors of the float32
+evaluation; the kernels hold the printed values.
 """
 import numpy as np
 from scipy.optimize import linprog
@@ -48,6 +50,38 @@ def eval_f32(c, t):
     return np.float32(t + np.float32(t * s) * p)
 
 
+def fit_anchor(deg: int = 3, n: int = 8000):
+    """atan(t) on [0, 1] as t * P(t^2) with P of degree `deg`, minimising the
+    maximum ABSOLUTE error: the anchor pixel of a warped patch needs its
+    angle only to a small fraction of a pixel, and without the reduction to
+    [0, tan(pi/8)] the polynomial costs fewer instructions."""
+    t = np.linspace(0.0, 1.0, n + 1)
+    s = t * t
+    A = np.stack([t * s ** k for k in range(deg + 1)], axis=1)
+    f = np.arctan(t)
+    cs = np.abs(A).max(axis=0)
+    scale = 1e4
+    cobj = np.zeros(deg + 2)
+    cobj[-1] = 1.0
+    ones = np.ones((len(t), 1))
+    A_ub = np.vstack([np.hstack([scale * A / cs, -ones]), np.hstack([-scale * A / cs, -ones])])
+    b_ub = np.concatenate([scale * f, -scale * f])
+    res = linprog(cobj, A_ub=A_ub, b_ub=b_ub,
+                  bounds=[(None, None)] * (deg + 1) + [(0, None)], method="highs")
+    if res.status != 0:
+        raise RuntimeError(res.message)
+    return np.float32(res.x[:-1] / cs), float(res.x[-1]) / scale
+
+
+def eval_anchor_f32(c, t):
+    t = np.asarray(t, dtype=np.float32)
+    s = t * t
+    p = np.float32(c[-1])
+    for k in range(len(c) - 2, -1, -1):
+        p = np.float32(p * s + c[k])
+    return np.float32(t * p)
+
+
 if __name__ == "__main__":
     c, e = fit()
     t = np.linspace(1e-6, T_MAX, 2_000_001).astype(np.float32)
@@ -55,3 +89,8 @@ if __name__ == "__main__":
     rel = np.abs(eval_f32(c, t).astype(np.float64) - ref) / ref
     print("coefficients (c0..c3):", ", ".join(f"{float(x):.9e}f" for x in c))
     print(f"exact-arithmetic relative error {e:.3e}, float32 evaluation {rel.max():.3e}")
+    ca, ea = fit_anchor()
+    t = np.linspace(0.0, 1.0, 2_000_001).astype(np.float32)
+    err = np.abs(eval_anchor_f32(ca, t).astype(np.float64) - np.arctan(t.astype(np.float64)))
+    print("anchor coefficients (a0..a3):", ", ".join(f"{float(x):.9e}f" for x in ca))
+    print(f"anchor: exact-arithmetic absolute error {ea:.3e} rad, float32 evaluation {err.max():.3e} rad")

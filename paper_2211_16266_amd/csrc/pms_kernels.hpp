@@ -286,6 +286,26 @@ __device__ __forceinline__ float atan2_full(float y, float x)
     return copysignf(r, y);
 }
 
+// atan2 to within 8.2e-5 rad for any arguments (both zero give 0), for the
+// choice of an anchor pixel, which needs the angle only to a small fraction
+// of a pixel: octant reduction to t in [0, 1] and a degree-3 polynomial
+// fitted there for minimum absolute error (atan_coeffs.py, fit_anchor).
+__device__ __forceinline__ float atan2_anchor(float y, float x)
+{
+    const float ax = fabsf(x), ay = fabsf(y);
+    const float mx = fmaxf(fmaxf(ax, ay), 1e-30f);
+    const float mn = fminf(ax, ay);
+    const float t = mn * __builtin_amdgcn_rcpf(mx);
+    const float u = t * t;
+    float p = fmaf(u, -3.898651525e-02f, 1.462644637e-01f);
+    p = fmaf(p, u, -3.211749792e-01f);
+    p = fmaf(p, u, 9.992138147e-01f);
+    float r = t * p;
+    r = ay > ax ? 1.57079632679489662f - r : r;
+    r = x < 0.0f ? 3.14159265358979324f - r : r;
+    return copysignf(r, y);
+}
+
 // For x > 1e-30 and |y| rcp(x) <= tan(pi/8), atan2_full(y, x) computes
 // exactly copysign(atan_core(|y| rcp(x)), y) = atan_core(y rcp(x)). Sample
 // angles measured from the anchor take this short form when a bound shows
@@ -433,9 +453,11 @@ __device__ __forceinline__ void view_setup(const SweepArgs &A, const Patch<SPL> 
         const double rb = fma(V.R[3 * a], pt.bp64[0], fma(V.R[3 * a + 1], pt.bp64[1], V.R[3 * a + 2] * pt.bp64[2]));
         yc[a] = fma(mc, rb, -V.t[a] * nbp);
     }
-    // anchor: the pixel nearest to the warped centre
-    const float lamc = atan2_full((float)yc[0], (float)yc[2]);
-    const float phic = atan2_full((float)-yc[1], __builtin_amdgcn_sqrtf((float)(yc[0] * yc[0] + yc[2] * yc[2])));
+    // anchor: the pixel nearest to the warped centre, up to the error of
+    // the anchor atan2 (a pixel next to it at worst; the short-form tests
+    // below use the centre's actual offset from it)
+    const float lamc = atan2_anchor((float)yc[0], (float)yc[2]);
+    const float phic = atan2_anchor((float)-yc[1], __builtin_amdgcn_sqrtf((float)(yc[0] * yc[0] + yc[2] * yc[2])));
     int U0 = (int)floorf(fmaf(lamc, A.kx, A.cx) + 0.5f);
     U0 = U0 >= A.W ? U0 - A.W : (U0 < 0 ? U0 + A.W : U0);
     int V0 = (int)floorf(fmaf(phic, A.ky, A.cy) + 0.5f);
@@ -449,13 +471,17 @@ __device__ __forceinline__ void view_setup(const SweepArgs &A, const Patch<SPL> 
         o.base = (V0p * A.Wp + U0p) * (int)sizeof(float4);
     }
     // centre turned about the vertical by -lam0 (FP64). Its longitude is
-    // within half a pixel of lam0, so yr2 > 0 and |yr0| << yr2, and the
-    // horizontal length is yr2 + yr0^2 / (2 yr2) to FP64 precision.
+    // within a pixel and a half of lam0 (half a pixel, plus the anchor
+    // atan2's error), so yr2 > 0 and tau = yr0 / yr2 is small, and the
+    // horizontal length yr2 sqrt(1 + tau^2) is yr2 + q - q^2 / (2 yr2), q =
+    // yr2 tau^2 / 2, to FP64 precision (the next term is yr2 tau^6 / 16).
     const double yr0 = fma(lam0.y, yc[0], -lam0.x * yc[2]);
     const double yr2 = fma(lam0.x, yc[0], lam0.y * yc[2]);
     o.y0c = (float)yr0;
     o.y2c = (float)yr2;
-    const double hzc = yr2 + (double)(0.5f * o.y0c * o.y0c * __builtin_amdgcn_rcpf(o.y2c));
+    const float ry2 = __builtin_amdgcn_rcpf(o.y2c);
+    const float q = 0.5f * o.y0c * o.y0c * ry2;
+    const double hzc = yr2 + (double)fmaf(-0.5f * q * q, ry2, q);
     // centre: sin and cos of (latitude - phi0), scaled by the ray length
     o.sdc = (float)fma(-yc[1], phi0.y, -hzc * phi0.x);
     o.cdc = (float)fma(hzc, phi0.y, -yc[1] * phi0.x);
