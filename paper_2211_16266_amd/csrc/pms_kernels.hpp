@@ -437,9 +437,32 @@ __device__ __forceinline__ void stage_poses(const SweepArgs &A)
     __syncthreads();
 }
 
+// R_j b_p of the views a lane sets up (view jb + lane in round jb / LPP):
+// it does not depend on the plane, so each lane forms it once per pixel and
+// keeps it in LDS (its own slots; registers are spoken for).
+template <int LPP>
+__device__ __forceinline__ double (&ray_stage())[MAXV / LPP][3][BLOCK]
+{
+    __shared__ double stage[MAXV / LPP][3][BLOCK];
+    return stage;
+}
+
+template <int LPP>
+__device__ __forceinline__ void stage_rays(const SweepArgs &A, const double bp[3], int lane)
+{
+    for (int jb = 0; jb < A.n_views; jb += LPP) {
+        if (jb + lane >= A.n_views) break;
+        const ViewPoseD &V = pose_stage().d[jb + lane];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            ray_stage<LPP>()[jb / LPP][a][threadIdx.x] =
+                fma(V.R[3 * a], bp[0], fma(V.R[3 * a + 1], bp[1], V.R[3 * a + 2] * bp[2]));
+    }
+}
+
 // Sets up view j for plane (n, c) at the pixel of `pt`; mc = -c. Reads the
-// poses from the workgroup's stage.
-template <int SPL>
+// poses from the workgroup's stage and R_j b_p from the lane's ray stage.
+template <int LPP, int SPL>
 __device__ __forceinline__ void view_setup(const SweepArgs &A, const Patch<SPL> &pt, int j, double mc,
                                            double nbp, float n0, float n1, float n2, ViewSetup &o)
 {
@@ -450,7 +473,7 @@ __device__ __forceinline__ void view_setup(const SweepArgs &A, const Patch<SPL> 
     double yc[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const double rb = fma(V.R[3 * a], pt.bp64[0], fma(V.R[3 * a + 1], pt.bp64[1], V.R[3 * a + 2] * pt.bp64[2]));
+        const double rb = ray_stage<LPP>()[j / LPP][a][threadIdx.x];
         yc[a] = fma(mc, rb, -V.t[a] * nbp);
     }
     // anchor: the pixel nearest to the warped centre, up to the error of
@@ -669,7 +692,7 @@ __device__ __forceinline__ float evaluate(const SweepArgs &A, const Patch<SPL> &
             // sample loops)
             const double nbp_r = (double)n0 * pt.bp64[0] + (double)n1 * pt.bp64[1] + (double)n2 * pt.bp64[2];
             ViewSetup mine;
-            view_setup<SPL>(A, pt, jb + lane, -((double)d * nbp_r), nbp_r, n0, n1, n2, mine);
+            view_setup<LPP, SPL>(A, pt, jb + lane, -((double)d * nbp_r), nbp_r, n0, n1, n2, mine);
             put_setup(setup_lds, threadIdx.x, mine);
         }
         __builtin_amdgcn_wave_barrier();
@@ -719,11 +742,17 @@ __device__ __forceinline__ float evaluate(const SweepArgs &A, const Patch<SPL> &
             // far; slots past top_k only collect larger costs and are never
             // summed
             unsigned cb = __float_as_uint(cj);
+            if (A.top_k <= 2) {
+                // (the usual two of four views: the other slots stay at 3)
+                top[1] = min(top[1], max(top[0], cb));
+                top[0] = min(top[0], cb);
+            } else {
 #pragma unroll
-            for (int i = 0; i < MAXK; ++i) {
-                const unsigned lo = min(top[i], cb), hi = max(top[i], cb);
-                top[i] = lo;
-                cb = hi;
+                for (int i = 0; i < MAXK; ++i) {
+                    const unsigned lo = min(top[i], cb), hi = max(top[i], cb);
+                    top[i] = lo;
+                    cb = hi;
+                }
             }
             if (!VIEWS) {
                 const int have = A.top_k - (A.n_views - 1 - j);  // evaluated costs in the bound
@@ -979,6 +1008,7 @@ __device__ __forceinline__ void init_tile(const SweepArgs &A, int tile)
     }
     Patch<SPL> pt;
     patch_setup<TR, LPP, SPL>(A, x, y, lane, pt);
+    stage_rays<LPP>(A, pt.bp64, lane);
     float u[4];
     uniforms(A.seed, (unsigned long long)idx, 0ULL, 0ULL, u);
     const float rho = fmaf(u[0], A.inv_dmin - A.inv_dmax, A.inv_dmax);
@@ -1044,6 +1074,7 @@ __device__ __forceinline__ void halfsweep_tile(const SweepArgs &A, int tile, int
 
     Patch<SPL> pt;
     patch_setup<TR, LPP, SPL>(A, x, y, lane, pt);
+    stage_rays<LPP>(A, pt.bp64, lane);
     const float4 cur = A.state[idx];
     float bd = cur.w, bn0 = cur.x, bn1 = cur.y, bn2 = cur.z;
     float bc = A.cost[idx];
@@ -1165,6 +1196,7 @@ __device__ __forceinline__ void eval_tile(const SweepArgs &A, int tile)
     }
     Patch<SPL> pt;
     patch_setup<TR, LPP, SPL>(A, x, y, lane, pt);
+    stage_rays<LPP>(A, pt.bp64, lane);
     float c;
     if (A.view_out[0])
         c = evaluate<PT, LPP, SPL, FULL, true>(A, pt, d, A.in_n0[pin], A.in_n1[pin], A.in_n2[pin], lane, pout);
