@@ -621,8 +621,8 @@ __device__ __forceinline__ float warp_samples(const SweepArgs &A, const Patch<SP
         // latitude stays within the poles, so the cell lies inside the
         // storage; the clamp only keeps every address there whatever the
         // inputs
-        const int off =
-            clamp0_int((int)((unsigned)(__mul24(floor_int(vl), A.Wp) + floor_int(ul)) << 4) + V.base, last);
+        const int off = clamp0_int(
+            (int)(((unsigned)(__mul24(floor_int(vl), A.Wp) + floor_int(ul)) << 4) + (unsigned)V.base), last);
         s[i] = bilinear(img, off, au, av);
         sum += FULL ? s[i] : s[i] * pt.wt[i];
     }
