@@ -7,6 +7,10 @@
   2 GiB: one densify iteration on seeded textured images gives planes in
   range facing the camera, and at sampled pixels the stored cost is the
   oracle's cost of the stored plane.
+* Degenerate inputs of the method: a constant reference (every view
+  invalid: the random initial planes remain, the oracle's own), and
+  neighbours seen from the reference's centre (the warp no longer depends
+  on the plane: only the costs are unique).
 """
 import os
 import re
@@ -123,3 +127,52 @@ def test_maximum_height_densify(pms):
                                nn[:, k, x].astype(np.float64))[0] for nb, (Rj, tj) in zip(f64[1:], R)]
         co = oracle.aggregate(vc, params["top_k"])
         assert abs(co - cn[k, x]) <= 1e-4 or min(vc) >= 2.0 and cn[k, x] == 2.0, (x, y, co, cn[k, x])
+
+
+def test_textureless_reference_keeps_the_random_planes(pms):
+    """A constant reference has no patch variance: every view is invalid
+    (cost 2), no hypothesis is strictly better than another, and the random
+    initial planes remain; the oracle draws the same ones (Philox)."""
+    W, H = 64, 32
+    params = dict(synth.params_for("box_room"), iterations=2, seed=5)
+    poses = _poses(2, seed=4)
+    imgs = [np.full((H, W), 0.5, dtype=np.float32)] + [_texture(W, H, seed=k) for k in (1, 2)]
+    dev = [torch.from_numpy(a).cuda() for a in imgs]
+    say("densify 64x32, constant reference")
+    d, n, c = (t.cpu().numpy() for t in pms.densify(dev[0], dev[1:], poses[0], poses[1:], params))
+    f64 = [a.astype(np.float64) for a in imgs]
+    do, no, co = oracle.densify(f64[0], f64[1:], poses[0], poses[1:], params)
+    r = (params["patch_size"] - 1) // 2
+    band = slice(r, H - r)
+    assert np.all(c[band] == 2.0) and np.all(co[band] == 2.0)
+    assert np.all(d[band] > 0)
+    np.testing.assert_allclose(d[band], do[band], rtol=1e-5)
+    np.testing.assert_allclose(n[:, band], no[:, band], atol=1e-5)
+
+
+def test_zero_baseline_costs(pms):
+    """Neighbours seen from the reference's own centre (other yaw only): the
+    warp no longer depends on the plane, so every hypothesis scores the same
+    and the depths are not determined; what is unique is the cost, close to
+    0 on the textured scene, and every plane must still be valid."""
+    w = synth.scaled("box_room", 128, seed=3)
+    c0 = -w.poses[w.ref][0].T @ w.poses[w.ref][1]
+    poses = [w.poses[w.ref]] + [synth.camera_pose(c0, yaw) for yaw in (0.7, -1.9)]
+    scene, _, _, _, _ = synth.scene_and_poses("box_room", 3)
+    imgs = [w.images[w.ref]] + [synth.render(scene, p, w.W, w.H, ss=4)[0] for p in poses[1:]]
+    dev = [torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda() for a in imgs]
+    params = dict(w.params, iterations=2)
+    say("densify 128x64, zero baseline")
+    d, n, c = (t.cpu().numpy() for t in pms.densify(dev[0], dev[1:], poses[0], poses[1:], params))
+    r = (params["patch_size"] - 1) // 2
+    band = slice(r, w.H - r)
+    assert np.all((d[band] >= params["depth_min"]) & (d[band] <= params["depth_max"]))
+    valid = c[band] < 2.0
+    assert valid.mean() > 0.9
+    assert np.median(c[band][valid]) < 0.05
+    # the oracle scores the GPU's planes the same
+    f64 = [a.astype(np.float64) for a in imgs]
+    co, _ = oracle.eval_cost(f64[0], f64[1:], poses[0], poses[1:], params, d.astype(np.float64),
+                             n.astype(np.float64))
+    both = (c < 2.0) & (co < 2.0)
+    assert np.abs(c[both] - co[both]).max() <= 1e-4
