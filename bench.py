@@ -13,8 +13,12 @@ A step is one full pms_densify call (reference statistics, random
 initialisation, 16 half-sweeps, output, consistency) with every input
 resident in HBM. Prints ONE JSON line on stdout; progress goes to stderr.
 
-Two more sections ride on the same line (skip them with --no-batch /
---serve-horizon 0):
+More sections ride on the same line (skip them with --no-quality /
+--no-batch / --serve-horizon 0):
+* "quality_3840": the 3840x1920 8-bit courtyard keyframe (6 neighbours,
+  15x15 patch sampled every 2nd pixel, 10 iterations, consistency against
+  4 maps of its window), timed over --quality-steps densify calls with
+  accuracy against the rendered ground truth.
 * "batch": 32 keyframe jobs (12 at 960x480, 12 at 1920x960, 8 at
   2880x1440, 3-6 neighbours each, hall generator and parameters) with
   FP16 images, as one prepared batch replayed as one HIP graph launch under
@@ -72,6 +76,9 @@ HBM_PEAK_GBS = 8000.0
 # own cost 4 + patch statistics 8 + the opposite colour's plane read once 16
 # + write-back of plane and cost 20
 HBM_BYTES_PER_UPDATE = 64
+# the half-sweep kernel of this workload (FP32 images, 4 lanes and 9 samples
+# per lane, every slot filled) as profilers name it
+HALFSWEEP_KERNEL = "k_tiles<1, 0, 4, 9, true>"
 
 
 def log(msg: str) -> None:
@@ -204,6 +211,48 @@ def _gt_accuracy(depth, gt, r):
     valid = d > 0
     ok = valid & (g > 0) & (np.abs(d - g) <= 0.01 * np.maximum(g, 1e-9))
     return float(valid.mean()), float(ok.sum() / max(valid.sum(), 1))
+
+
+def quality_section(args, torch, pms, synth, ctx) -> dict:
+    """The 3840x1920 8-bit courtyard (6 neighbours, 15x15 sparse patch, 10
+    iterations, consistency against 4 maps of the window), timed like the
+    headline on the same context."""
+    log("rendering courtyard_3840 (7 keyframes, 3840x1920, 8-bit)")
+    w = synth.workload("courtyard_3840", seed=args.seed)
+    params = dict(w.params)
+    dev = torch.device("cuda:0")
+    imgs = [torch.from_numpy(a).to(dev) for a in w.images]
+    log("densifying its 4 map keyframes (untimed)")
+    maps, map_poses = [], []
+    for i in w.maps:
+        others = [k for k in range(len(w.images)) if k != i]
+        d_i, _, _ = pms.densify(imgs[i], [imgs[k] for k in others], w.poses[i],
+                                [w.poses[k] for k in others], params, ctx=ctx)
+        maps.append(d_i)
+        map_poses.append(w.poses[i])
+    ref, nbrs = imgs[w.ref], [imgs[i] for i in w.nbrs]
+    rp, nps = w.poses[w.ref], [w.poses[i] for i in w.nbrs]
+    out = (torch.empty((w.H, w.W), device=dev), torch.empty((3, w.H, w.W), device=dev),
+           torch.empty((w.H, w.W), device=dev))
+
+    def step():
+        pms.densify(ref, nbrs, rp, nps, params, maps=maps, map_poses=map_poses, out=out, ctx=ctx)
+
+    step()
+    torch.cuda.synchronize()
+    K = max(1, args.quality_steps)
+    t0 = time.perf_counter()
+    for _ in range(K):
+        step()
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / K
+    r = (params["patch_size"] - 1) // 2
+    comp, acc = _gt_accuracy(out[0].cpu().numpy(), w.gt_depth[w.ref], r)
+    return {"workload": "courtyard_3840: 3840x1920 u8, 6 neighbours, 15x15/2 (64 samples), "
+                        "10 iterations, consistency vs 4 maps",
+            "keyframes_per_s": 1.0 / t, "ms_per_keyframe": t * 1e3, "steps": K,
+            "schedule": ctx.get_schedule(),
+            "completeness": comp, "within_1pct_of_gt": acc}
 
 
 def batch_section(args, torch, pms, synth, pool, ctx) -> dict:
@@ -496,7 +545,7 @@ def counter_summary(fetch_dir: str, write_dir: str, probe_bytes: int, commands: 
     out = {}
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         rows = per_dispatch(d, counter)
-        hs = [v for n, v in rows if "k_tiles<1," in n]
+        hs = [v for n, v in rows if HALFSWEEP_KERNEL in n]
         probe = max(v for n, v in rows if "pms::" not in n)
         out[counter] = {"halfsweep_kib": sum(hs) / len(hs), "dispatches": len(hs),
                         "probe_kib": probe, "scale": probe_bytes / 1024.0 / probe}
@@ -562,6 +611,8 @@ def main() -> int:
     ap.add_argument("--cpu-budget", type=float, default=12.0,
                     help="wall seconds of oracle work for the CPU baseline (0 = skip)")
     ap.add_argument("--no-batch", action="store_true", help="skip the mixed FP16 batch section")
+    ap.add_argument("--no-quality", action="store_true", help="skip the 3840x1920 8-bit section")
+    ap.add_argument("--quality-steps", type=int, default=3)
     ap.add_argument("--no-tune", action="store_true", help="keep the default tile shape")
     ap.add_argument("--schedule", default=None, metavar="WAVE_ROWS,WAVES_X",
                     help="use this tile shape instead of autotuning (e.g. 4,2)")
@@ -586,7 +637,7 @@ def main() -> int:
     if args.counter_summary:
         fetch_dir, write_dir, sched = args.counter_summary
         cmd = ("rocprofv3 --pmc {c} --output-format csv -d gpurun_out/pmc_{c} -o pmc -- python3 "
-               "bench.py --steps 2 --warmup 0 --cpu-budget 0 --no-batch --serve-horizon 0 "
+               "bench.py --steps 2 --warmup 0 --cpu-budget 0 --no-quality --no-batch --serve-horizon 0 "
                "--copy-probe 268435456 --schedule " + sched)
         print(counter_summary(fetch_dir, write_dir, 268435456,
                               [cmd.format(c="FETCH_SIZE"), cmd.format(c="WRITE_SIZE")],
@@ -736,6 +787,8 @@ def main() -> int:
             "hbm_frac": hbm_bytes / avg_half_s / 1e9 / HBM_PEAK_GBS,
         },
     }
+    if not args.no_quality:
+        result["quality_3840"] = quality_section(args, torch, pms, synth, ctx)
     pool = None
     if not args.no_batch or args.serve_horizon > 0:
         log("rendering the mixed pool (7-keyframe hall windows at 960, 1920, 2880)")
