@@ -63,7 +63,9 @@ constexpr int BLOCK = 256;    // threads per workgroup (4 waves)
 // Occupancy target of the PatchMatch kernels (waves per SIMD): 4 for up to
 // 9 samples per lane, where the compiler would otherwise settle for 3 waves
 // to avoid a couple of spill slots outside the sample loop; the larger
-// variants keep the compiler's choice.
+// variants keep the compiler's choice (2 waves, which hold the short and
+// the general sample forms without spills: forcing 3 spills inside the
+// sample loop and runs slower).
 #define PMS_OCCUPANCY(SPL) __attribute__((amdgpu_waves_per_eu((SPL) <= 9 ? 4 : 1, 8)))
 // Re-laid-out neighbour image: H + 1 rows of 2W + 4 bilinear cells (16
 // bytes); logical column x is stored at x + W/2 + 2, logical row y at y + 1.
@@ -704,10 +706,7 @@ __device__ __forceinline__ float evaluate(const SweepArgs &A, const Patch<SPL> &
             const __amdgpu_buffer_rsrc_t img = make_rsrc(A.pad[j], A.pad_bytes);
             float s[SPL];
             float sum;
-            // (the short forms are compiled in for up to 9 samples per lane
-            // only: the larger variants cannot hold more than one copy at
-            // their occupancy)
-            if (SPL <= 9 && __all(V.short_ok & SHORT_LAT)) {
+            if (__all(V.short_ok & SHORT_LAT)) {
                 if (__all(V.short_ok & SHORT_LON))
                     sum = warp_samples<true, true, SPL, FULL>(A, pt, V, img, last, s);
                 else
