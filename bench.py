@@ -13,8 +13,12 @@ A step is one full pms_densify call (reference statistics, random
 initialisation, 16 half-sweeps, output, consistency) with every input
 resident in HBM. Prints ONE JSON line on stdout; progress goes to stderr.
 
-More sections ride on the same line (skip them with --no-quality /
---no-batch / --serve-horizon 0):
+More sections ride on the same line (skip them with --lat-runs 0 /
+--no-quality / --no-batch / --serve-horizon 0):
+* "latency_runs_ms": p50/p99 of 50 single calls of the same keyframe after
+  5 untimed ones, each bracketed by HIP events: with every input resident,
+  and with the five keyframe images uploaded from pinned host memory
+  inside the bracket.
 * "quality_3840": the 3840x1920 8-bit courtyard keyframe (6 neighbours,
   15x15 patch sampled every 2nd pixel, 10 iterations, consistency against
   4 maps of its window), timed over --quality-steps densify calls with
@@ -211,6 +215,43 @@ def _gt_accuracy(depth, gt, r):
     valid = d > 0
     ok = valid & (g > 0) & (np.abs(d - g) <= 0.01 * np.maximum(g, 1e-9))
     return float(valid.mean()), float(ok.sum() / max(valid.sum(), 1))
+
+
+def latency_section(args, torch, step, host_imgs, dev_imgs) -> dict:
+    """Per-call latency of the headline keyframe on a warm context: --lat-warmup
+    untimed and --lat-runs timed calls, each bracketed by events on the
+    stream it runs on, first with every input resident in HBM, then with
+    the five keyframe images uploaded from pinned host memory inside the
+    bracket (the neighbour depth maps stay resident: they are this
+    pipeline's own earlier outputs)."""
+    stream = torch.cuda.current_stream()
+
+    def runs(upload):
+        for _ in range(args.lat_warmup):
+            if upload:
+                for h, d in zip(host_imgs, dev_imgs):
+                    d.copy_(h, non_blocking=True)
+            step()
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(args.lat_runs):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            if upload:
+                for h, d in zip(host_imgs, dev_imgs):
+                    d.copy_(h, non_blocking=True)
+            step()
+            b.record(stream)
+            b.synchronize()
+            ms.append(a.elapsed_time(b))
+        ms = np.array(ms)
+        return {"runs": len(ms), "p50": float(np.percentile(ms, 50)),
+                "p99": float(np.percentile(ms, 99)), "mean": float(ms.mean())}
+
+    log(f"latency: {args.lat_warmup} + {args.lat_runs} calls resident, then with uploads")
+    upload_bytes = sum(h.numel() * h.element_size() for h in host_imgs)
+    return {"resident": runs(False),
+            "with_h2d_upload": dict(runs(True), bytes_uploaded=upload_bytes)}
 
 
 def quality_section(args, torch, pms, synth, ctx) -> dict:
@@ -613,6 +654,9 @@ def main() -> int:
     ap.add_argument("--no-batch", action="store_true", help="skip the mixed FP16 batch section")
     ap.add_argument("--no-quality", action="store_true", help="skip the 3840x1920 8-bit section")
     ap.add_argument("--quality-steps", type=int, default=3)
+    ap.add_argument("--lat-runs", type=int, default=50,
+                    help="timed calls of the latency section (0 skips it)")
+    ap.add_argument("--lat-warmup", type=int, default=5)
     ap.add_argument("--no-tune", action="store_true", help="keep the default tile shape")
     ap.add_argument("--schedule", default=None, metavar="WAVE_ROWS,WAVES_X",
                     help="use this tile shape instead of autotuning (e.g. 4,2)")
@@ -637,7 +681,7 @@ def main() -> int:
     if args.counter_summary:
         fetch_dir, write_dir, sched = args.counter_summary
         cmd = ("rocprofv3 --pmc {c} --output-format csv -d gpurun_out/pmc_{c} -o pmc -- python3 "
-               "bench.py --steps 2 --warmup 0 --cpu-budget 0 --no-quality --no-batch --serve-horizon 0 "
+               "bench.py --steps 2 --warmup 0 --cpu-budget 0 --no-quality --lat-runs 0 --no-batch --serve-horizon 0 "
                "--copy-probe 268435456 --schedule " + sched)
         print(counter_summary(fetch_dir, write_dir, 268435456,
                               [cmd.format(c="FETCH_SIZE"), cmd.format(c="WRITE_SIZE")],
@@ -764,6 +808,9 @@ def main() -> int:
                    "consistency_maps": len(maps), "seed": args.seed, "schedule": schedule},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "mean": float(lat.mean())},
+        "accuracy": dict(zip(("completeness", "within_1pct_of_gt"),
+                             _gt_accuracy(out[0].cpu().numpy(), w.gt_depth[w.ref],
+                                          (params["patch_size"] - 1) // 2))),
         "ncc_evals_per_s": evals_per_kf * kfps,
         "kernels_ms_per_step": {k: v[1] / K for k, v in kern.items()},
         "roofline": {
@@ -787,6 +834,10 @@ def main() -> int:
             "hbm_frac": hbm_bytes / avg_half_s / 1e9 / HBM_PEAK_GBS,
         },
     }
+    if args.lat_runs > 0:
+        host = [torch.from_numpy(w.images[i]).pin_memory() for i in window]
+        result["latency_runs_ms"] = latency_section(args, torch, step, host,
+                                                    [imgs[i] for i in window])
     if not args.no_quality:
         result["quality_3840"] = quality_section(args, torch, pms, synth, ctx)
     pool = None
