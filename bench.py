@@ -38,8 +38,9 @@ More sections ride on the same line (skip them with --lat-runs 0 /
   latency from arrival to result, mean batch occupancy, accuracy against
   ground truth beside the plain FP32 path on the same keyframes; three
   served jobs re-run alone must match bit for bit.
-* "serving_random_init": the same request stream with random
-  initialisation and the full iterations for every keyframe.
+* "serving_random_init": the same kind of request stream over
+  --serve-random-horizon seconds with random initialisation and the full
+  iterations for every keyframe.
 """
 from __future__ import annotations
 
@@ -412,26 +413,28 @@ def batch_section(args, torch, pms, synth, pool, ctx) -> dict:
                                 "speedup": t_small_plain / t_small_batch}}
 
 
-def serving_section(args, torch, pms, synth, pool, ctx, warm: bool) -> dict:
+def serving_section(args, torch, pms, synth, pool, ctx, warm: bool, horizon: float) -> dict:
     """Keyframe streams through the continuous-batching server. A keyframe
     whose stream predecessor is already done starts from the predecessor's
     planes carried over by plane-map warping (Sec. III-B) and runs
     --serve-warm-iters iterations; otherwise it starts from random planes
     with the full iterations. Accuracy against the rendered ground truth is
-    measured on every 8th served keyframe and on the same keyframes
+    measured on every 8th served keyframe (fewer past 360 requests, about
+    45 in all) and on the same keyframes
     densified by the plain FP32 path with the full iterations."""
     from paper_2211_16266_amd import serving
     dev = torch.device("cuda:0")
     imgs32 = {W: [torch.from_numpy(a).to(dev) for a in w.images] for W, w in pool.items()}
     imgs16 = {W: [t.half() for t in ts] for W, ts in imgs32.items()}
-    reqs = synth.stream_requests(args.serve_streams, args.serve_rate, args.serve_horizon,
+    reqs = synth.stream_requests(args.serve_streams, args.serve_rate, horizon,
                                  seed=args.seed + 7)
     warp_ctx = pms.Context(0)
     server = pms.Server(int(args.serve_arena_gib * 2**30), max_jobs=args.serve_max_jobs,
                         ctx=pms.Context(0))
     latest = {}   # stream -> (k, width, keyframe, depth, normal) of its newest finished keyframe
     count = {"warm": 0, "cold": 0}
-    sample_every = 8
+    # about 45 keyframes are checked whatever the horizon
+    sample_every = max(8, len(reqs) // 45)
     samples = []  # (MixedJob, warm, outputs)
 
     def factory(i, s, k, mj):
@@ -493,7 +496,7 @@ def serving_section(args, torch, pms, synth, pool, ctx, warm: bool) -> dict:
         return k == 0 or (s in latest and latest[s][0] >= k - 1)
 
     log(f"serving {len(requests)} keyframes from {args.serve_streams} streams at "
-        f"{args.serve_rate}/s each over {args.serve_horizon:.0f} s "
+        f"{args.serve_rate}/s each over {horizon:.0f} s "
         f"({'warm starts from the stream predecessor' if warm else 'random initialisation'})")
     out = serving.run(server, requests, on_done=on_done, log=log, keep_jobs=False,
                       ready=ready if warm else None)
@@ -538,7 +541,7 @@ def serving_section(args, torch, pms, synth, pool, ctx, warm: bool) -> dict:
                         "one width per stream from 960/1920/2880, N~U{3..6}, f16 images",
             "warm_start": warm, "warm_iterations": args.serve_warm_iters if warm else None,
             "warm_started": count["warm"], "cold_started": count["cold"],
-            "horizon_s": args.serve_horizon, "requests": out["requests"],
+            "horizon_s": horizon, "requests": out["requests"],
             "offered_keyframes_per_s": offered,
             "keyframes_per_s": out["keyframes_per_s"], "wall_s": out["wall_s"],
             "latency_ms": {"p50": out["p50_ms"], "p99": out["p99_ms"], "mean": out["mean_ms"]},
@@ -663,6 +666,8 @@ def main() -> int:
     ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--serve-horizon", type=float, default=15.0,
                     help="seconds of request arrivals in the serving section (0 = skip)")
+    ap.add_argument("--serve-random-horizon", type=float, default=15.0,
+                    help="seconds of arrivals of the random-initialisation serving run (0 skips it)")
     ap.add_argument("--serve-rate", type=float, default=3.0, help="arrivals per second per stream")
     ap.add_argument("--serve-streams", type=int, default=8)
     ap.add_argument("--serve-max-jobs", type=int, default=8)
@@ -847,10 +852,11 @@ def main() -> int:
     if not args.no_batch:
         result["batch"] = batch_section(args, torch, pms, synth, pool, ctx)
     if args.serve_horizon > 0:
-        result["serving"] = serving_section(args, torch, pms, synth, pool, ctx, warm=not args.serve_cold)
-        if not args.serve_cold:
+        result["serving"] = serving_section(args, torch, pms, synth, pool, ctx, warm=not args.serve_cold,
+                                            horizon=args.serve_horizon)
+        if not args.serve_cold and args.serve_random_horizon > 0:
             result["serving_random_init"] = serving_section(args, torch, pms, synth, pool, ctx,
-                                                            warm=False)
+                                                            warm=False, horizon=args.serve_random_horizon)
     if args.cpu_budget > 0:
         threads = min(os.cpu_count() or 1, 16)
         log(f"cpu baseline: oracle on {threads} threads, ~{args.cpu_budget:.0f} s")
