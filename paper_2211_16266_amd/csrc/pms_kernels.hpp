@@ -594,11 +594,13 @@ __device__ __forceinline__ float warp_samples(const SweepArgs &A, const Patch<SP
 #pragma unroll
     for (int i = 0; i < SPL; ++i) {
         const float bx = pt.b[i][0], by = pt.b[i][1], bz = pt.b[i][2];
-        // the turned homography on the offset from the centre bearing
-        const float e0 = fmaf(V.h[0], bx, fmaf(V.h[1], by, V.h[2] * bz));
+        // the turned homography on the offset from the centre bearing; the
+        // x row starts from the centre's x, which is small as well (the
+        // anchor is within a pixel and a half of the centre's longitude)
+        const float y0 = fmaf(V.h[0], bx, fmaf(V.h[1], by, fmaf(V.h[2], bz, y0c)));
         const float e1 = fmaf(V.h[3], bx, fmaf(V.h[4], by, V.h[5] * bz));
         const float e2 = fmaf(V.h[6], bx, fmaf(V.h[7], by, V.h[8] * bz));
-        const float y0 = y0c + e0, y2 = y2c + e2;
+        const float y2 = y2c + e2;
         // tangent of the longitude offset, and hz - hzc without cancellation:
         // with u = tau^2, hz = y2 + y2 u G(u) and hzc = y2c + kc, so
         // hz - hzc = (e2 - kc) + y2 u G(u) while |tau| <= tan(pi/8) (always
