@@ -13,8 +13,14 @@ A step is one full pms_densify call (reference statistics, random
 initialisation, 16 half-sweeps, output, consistency) with every input
 resident in HBM. Prints ONE JSON line on stdout; progress goes to stderr.
 
-More sections ride on the same line (skip them with --lat-runs 0 /
---no-quality / --no-batch / --serve-horizon 0):
+More sections ride on the same line (skip them with --no-next /
+--lat-runs 0 / --no-quality / --no-batch / --serve-horizon 0):
+* "next_rows": the calls beside densification at the headline's size, each
+  timed per call with ms, items/s and achieved GB/s of its algorithmic
+  bytes: plane-map warping of the result into a neighbour, the 5x5 median
+  post-filter (the median kernel inside a densify call), voxel fusion and
+  720x360 coverage of the window's 5 depth maps, and the view filter over
+  2^20 sparse points.
 * "latency_runs_ms": p50/p99 of 50 single calls of the same keyframe after
   5 untimed ones, each bracketed by HIP events: with every input resident,
   and with the five keyframe images uploaded from pinned host memory
@@ -253,6 +259,97 @@ def latency_section(args, torch, step, host_imgs, dev_imgs) -> dict:
     upload_bytes = sum(h.numel() * h.element_size() for h in host_imgs)
     return {"resident": runs(False),
             "with_h2d_upload": dict(runs(True), bytes_uploaded=upload_bytes)}
+
+
+# Algorithmic HBM bytes of the calls beside densification, per item: a
+# pixel of the 1920x960 map (warp, median), a point of the depth maps
+# (fuse, coverage) or a sparse point (view filter).
+NEXT_BYTES = {
+    # z-buffer clear 8, depth read 4, 64-bit atomic 8, z-buffer read 8,
+    # winner's plane gathered 16, plane written 16
+    "warp": 60,
+    # the plane state read once (16); the window re-reads hit the caches
+    "median": 16,
+    # 2 table slots of 16 cleared, depth read twice 8, CAS 8 + atomic min 8,
+    # key and order read back 16, keep byte 1
+    "fuse": 73,
+    # depth 4, keep byte 1, cover byte 1
+    "coverage": 6,
+    # one FP64 point 24
+    "view_filter": 24,
+}
+
+
+def next_rows_section(args, torch, pms, w, params, out, maps, map_poses, ctx) -> dict:
+    """The calls beside densification at the headline's size: plane-map
+    warping of the keyframe's result to a neighbour (Sec. III-B), the
+    median post-filter inside densify (Sec. III-C), voxel fusion and
+    panorama coverage of the window's 5 depth maps, and the view filter
+    (Eq. 1) over --vf-points sparse points. Each is timed with the
+    library's per-launch events over --next-reps calls."""
+    dev = out[0].device
+    H, W = out[0].shape
+    reps = max(1, args.next_reps)
+    res = {}
+
+    def timed(name, call, items, unit):
+        call()
+        torch.cuda.synchronize()
+        ctx.profile_enable(True)
+        ctx.profile_read(name)
+        for _ in range(reps):
+            call()
+        n, ms = ctx.profile_read(name)
+        ctx.profile_enable(False)
+        per = ms / max(n, 1)
+        gbs = items * NEXT_BYTES[name] / (per * 1e-3) / 1e9
+        res[name] = {"ms_per_call": per, "calls": n, f"{unit}_per_s": items / (per * 1e-3),
+                     "algorithmic_bytes_per_item": NEXT_BYTES[name], "achieved_GBs": gbs,
+                     "hbm_frac": gbs / HBM_PEAK_GBS}
+
+    log("next rows: warp, median, fuse, coverage, view filter")
+    wo = (torch.empty_like(out[0]), torch.empty_like(out[1]))
+    timed("warp", lambda: pms.warp_planes(out[0], out[1], w.poses[w.ref], map_poses[0], params,
+                                          out=wo, ctx=ctx), W * H, "pixels")
+    res["warp"]["valid_warped_fraction"] = float((wo[0] > 0).float().mean().item())
+
+    imgs = [torch.from_numpy(a).to(dev) for a in w.images]
+    ref, nbrs = imgs[w.ref], [imgs[i] for i in w.nbrs]
+    mp = dict(params, median_radius=2, median_rel=0.05)
+    mo = (torch.empty_like(out[0]), torch.empty_like(out[1]), torch.empty_like(out[2]))
+    timed("median", lambda: pms.densify(ref, nbrs, w.poses[w.ref], [w.poses[i] for i in w.nbrs], mp,
+                                        out=mo, ctx=ctx), W * H, "pixels")
+
+    depths = [out[0]] + list(maps)
+    poses = [w.poses[w.ref]] + list(map_poses)
+    kept = {}
+
+    def fuse():
+        kept["keep"], kept["n"] = pms.fuse(depths, poses, 0.02, ctx=ctx)
+
+    timed("fuse", fuse, W * H * len(depths), "points")
+    res["fuse"]["kept_points"] = kept["n"]
+    cov = {}
+
+    def coverage():
+        cov["n"], _ = pms.coverage(depths, poses, kept["keep"], w.poses[w.ref], ctx=ctx)
+
+    timed("coverage", coverage, W * H * len(depths), "points")
+    res["coverage"]["covered_fraction_720x360"] = cov["n"] / (720 * 360)
+
+    g = torch.Generator(device=dev)
+    g.manual_seed(args.seed)
+    centres = [-(np.asarray(R).T @ np.asarray(t)) for R, t in (w.poses[w.ref], map_poses[0])]
+    pts = (torch.rand((args.vf_points, 3), generator=g, device=dev, dtype=torch.float64) - 0.5) * 30.0
+    pts += torch.as_tensor(centres[0], device=dev)
+    vf = {}
+
+    def view_filter():
+        vf["r"] = pms.view_filter(centres[0], centres[1], pts, ctx=ctx)
+
+    timed("view_filter", view_filter, args.vf_points, "points")
+    res["view_filter"]["accepted"], res["view_filter"]["in_range"], res["view_filter"]["counted"] = vf["r"]
+    return res
 
 
 def quality_section(args, torch, pms, synth, ctx) -> dict:
@@ -660,6 +757,10 @@ def main() -> int:
     ap.add_argument("--lat-runs", type=int, default=50,
                     help="timed calls of the latency section (0 skips it)")
     ap.add_argument("--lat-warmup", type=int, default=5)
+    ap.add_argument("--no-next", action="store_true",
+                    help="skip the warp / median / fuse / coverage / view-filter timings")
+    ap.add_argument("--next-reps", type=int, default=10)
+    ap.add_argument("--vf-points", type=int, default=1 << 20)
     ap.add_argument("--no-tune", action="store_true", help="keep the default tile shape")
     ap.add_argument("--schedule", default=None, metavar="WAVE_ROWS,WAVES_X",
                     help="use this tile shape instead of autotuning (e.g. 4,2)")
@@ -686,7 +787,7 @@ def main() -> int:
     if args.counter_summary:
         fetch_dir, write_dir, sched = args.counter_summary
         cmd = ("rocprofv3 --pmc {c} --output-format csv -d gpurun_out/pmc_{c} -o pmc -- python3 "
-               "bench.py --steps 2 --warmup 0 --cpu-budget 0 --no-quality --lat-runs 0 --no-batch --serve-horizon 0 "
+               "bench.py --steps 2 --warmup 0 --cpu-budget 0 --no-quality --lat-runs 0 --no-next --no-batch --serve-horizon 0 "
                "--copy-probe 268435456 --schedule " + sched)
         print(counter_summary(fetch_dir, write_dir, 268435456,
                               [cmd.format(c="FETCH_SIZE"), cmd.format(c="WRITE_SIZE")],
@@ -839,6 +940,8 @@ def main() -> int:
             "hbm_frac": hbm_bytes / avg_half_s / 1e9 / HBM_PEAK_GBS,
         },
     }
+    if not args.no_next:
+        result["next_rows"] = next_rows_section(args, torch, pms, w, params, out, maps, map_poses, ctx)
     if args.lat_runs > 0:
         host = [torch.from_numpy(w.images[i]).pin_memory() for i in window]
         result["latency_runs_ms"] = latency_section(args, torch, step, host,

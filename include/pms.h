@@ -363,8 +363,10 @@ pms_status pms_philox_stream(pms_context *ctx, uint64_t key0, uint64_t key1, uin
    pms_profile_read synchronises on the recorded events, returns the launch
    count and total milliseconds of kernel `name` ("halfsweep", "init",
    "refstats", "finalize", "consistency", "eval", "io" for the image
-   re-layout and state copies, "batch" for whole graph launches) since the
-   last read, and clears them. A graph launch is timed as one "batch". */
+   re-layout and state copies, "batch" for whole graph launches, "median",
+   and one entry per call of the calls beside densification: "warp",
+   "fuse", "coverage", "view_filter") since the last read, and clears them.
+   A graph launch is timed as one "batch". */
 pms_status pms_profile_enable(pms_context *ctx, int32_t on);
 pms_status pms_profile_read(pms_context *ctx, const char *name, int64_t *launches,
                             double *total_ms);

@@ -29,13 +29,13 @@
 
 namespace {
 
-constexpr int kNumKernelKinds = 11;
+constexpr int kNumKernelKinds = 13;
 const char *const kKernelNames[kNumKernelKinds] = {"refstats", "init", "halfsweep", "finalize",
                                                    "consistency", "eval", "io", "batch", "warp",
-                                                   "median", "fuse"};
+                                                   "median", "fuse", "coverage", "view_filter"};
 enum KernelKind {
     KK_REFSTATS, KK_INIT, KK_HALFSWEEP, KK_FINALIZE, KK_CONSISTENCY, KK_EVAL, KK_IO, KK_GRAPH, KK_WARP,
-    KK_MEDIAN, KK_FUSE
+    KK_MEDIAN, KK_FUSE, KK_COVER, KK_VIEW
 };
 
 struct TimedLaunch {
@@ -1601,11 +1601,14 @@ pms_status pms_view_filter(pms_context *ctx, const double centre_a[3], const dou
     if (st != PMS_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     unsigned long long *counts = reinterpret_cast<unsigned long long *>(counts_out);
-    hipLaunchKernelGGL(pms::k_count_clear, dim3(1), dim3(64), 0, s, counts);
-    if (n_points > 0)
-        hipLaunchKernelGGL(pms::k_view_filter, dim3((unsigned)blocks_of(n_points)), dim3(pms::BLOCK), 0, s,
-                           centre_a[0], centre_a[1], centre_a[2], centre_b[0], centre_b[1], centre_b[2],
-                           points, (long long)n_points, min_deg, max_deg, counts);
+    {
+        LaunchTimer timer(ctx, KK_VIEW, s);
+        hipLaunchKernelGGL(pms::k_count_clear, dim3(1), dim3(64), 0, s, counts);
+        if (n_points > 0)
+            hipLaunchKernelGGL(pms::k_view_filter, dim3((unsigned)blocks_of(n_points)), dim3(pms::BLOCK), 0,
+                               s, centre_a[0], centre_a[1], centre_a[2], centre_b[0], centre_b[1],
+                               centre_b[2], points, (long long)n_points, min_deg, max_deg, counts);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(ctx, e, "view filter");
     return PMS_OK;
@@ -1708,7 +1711,7 @@ pms_status pms_coverage(pms_context *ctx, int32_t width, int32_t height, int32_t
     const long long pix = (long long)out_width * out_height;
     hipStream_t s = static_cast<hipStream_t>(stream);
     {
-        LaunchTimer timer(ctx, KK_FUSE, s);
+        LaunchTimer timer(ctx, KK_COVER, s);
         hipLaunchKernelGGL(pms::k_cover_clear, dim3((unsigned)blocks_of(pix)), dim3(pms::BLOCK), 0, s, A);
         hipLaunchKernelGGL(pms::k_cover_mark, dim3((unsigned)blocks_of(points)), dim3(pms::BLOCK), 0, s, A);
         hipLaunchKernelGGL(pms::k_cover_count, dim3((unsigned)blocks_of(pix)), dim3(pms::BLOCK), 0, s, A);

@@ -62,11 +62,13 @@ constexpr int BLOCK = 256;    // threads per workgroup (4 waves)
 
 // Occupancy target of the PatchMatch kernels (waves per SIMD): 4 for up to
 // 9 samples per lane, where the compiler would otherwise settle for 3 waves
-// to avoid a couple of spill slots outside the sample loop; the larger
-// variants keep the compiler's choice (2 waves, which hold the short and
-// the general sample forms without spills: forcing 3 spills inside the
-// sample loop and runs slower).
-#define PMS_OCCUPANCY(SPL) __attribute__((amdgpu_waves_per_eu((SPL) <= 9 ? 4 : 1, 8)))
+// to avoid a couple of spill slots outside the sample loop (3 for the
+// per-view cost evaluation, which keeps more state and cannot reach 4);
+// the larger variants keep the compiler's choice (2 waves, which hold the
+// short and the general sample forms without spills: forcing 3 spills
+// inside the sample loop and runs slower).
+#define PMS_OCCUPANCY(KIND, SPL) \
+    __attribute__((amdgpu_waves_per_eu((SPL) <= 9 ? ((KIND) == TK_EVAL ? 3 : 4) : 1, 8)))
 // Re-laid-out neighbour image: H + 1 rows of 2W + 4 bilinear cells (16
 // bytes); logical column x is stored at x + W/2 + 2, logical row y at y + 1.
 
@@ -1210,7 +1212,7 @@ enum TileKind { TK_INIT = 0, TK_HALFSWEEP = 1, TK_EVAL = 2 };
 
 // The PatchMatch kernels: every workgroup serves one tile of one job.
 template <int KIND, int DT, int LPP, int SPL, bool FULL>
-__global__ __launch_bounds__(BLOCK) PMS_OCCUPANCY(SPL) void k_tiles(Launch L)
+__global__ __launch_bounds__(BLOCK) PMS_OCCUPANCY(KIND, SPL) void k_tiles(Launch L)
 {
     int e, local;
     if (!block_entry(L, e, local)) return;
@@ -1259,18 +1261,63 @@ __device__ __forceinline__ float state_depth(const IoArgs &A, int x, int y)
     return d > 0.0f ? d : 0.0f;
 }
 
+// Drops the pixel's output when its depth d deviates from the window's
+// median (bit pattern m_bits) by more than median_rel of it.
+__device__ __forceinline__ void median_reject(const IoArgs &A, int x, int y, float d, unsigned m_bits)
+{
+    const double m = (double)__uint_as_float(m_bits);
+    if (fabs((double)d - m) > A.median_rel * m) {
+        A.depth[(long long)y * A.pd + x] = 0.0f;
+        A.n0[(long long)y * A.pn0 + x] = 0.0f;
+        A.n1[(long long)y * A.pn1 + x] = 0.0f;
+        A.n2[(long long)y * A.pn2 + x] = 0.0f;
+        A.cplane[(long long)y * A.pc + x] = 2.0f;
+    }
+}
+
 __device__ __forceinline__ void median_one(const IoArgs &A, long long i)
 {
     const int y = (int)(i / A.W), x = (int)(i - (long long)y * A.W);
     const float d = state_depth(A, x, y);
     if (!(d > 0.0f)) return;
     const int R = A.median_radius;
+    if (R <= 2) {
+        // windows up to 5x5 (the default) are read once into registers;
+        // a window pixel outside the image or the valid band counts as 0
+        float v[25];
+        int n = 0;
+#pragma unroll
+        for (int dy = -2; dy <= 2; ++dy)
+#pragma unroll
+            for (int dx = -2; dx <= 2; ++dx) {
+                const int yy = y + dy;
+                int xx = x + dx;
+                xx = xx < 0 ? xx + A.W : (xx >= A.W ? xx - A.W : xx);
+                const bool in = abs(dy) <= R && abs(dx) <= R && yy >= 0 && yy < A.H;
+                // (the row is clamped so that the read stays in the image)
+                const float vv = state_depth(A, xx, min(max(yy, 0), A.H - 1));
+                v[(dy + 2) * 5 + dx + 2] = in ? vv : 0.0f;
+                n += in && vv > 0.0f ? 1 : 0;
+            }
+        const int k = (n - 1) / 2;
+        unsigned lo = 1u, hi = 0x7f800000u;
+        while (lo < hi) {
+            const unsigned mid = lo + ((hi - lo) >> 1);
+            int c = 0;
+#pragma unroll
+            for (int q = 0; q < 25; ++q) c += (v[q] > 0.0f && __float_as_uint(v[q]) <= mid) ? 1 : 0;
+            if (c > k) hi = mid;
+            else lo = mid + 1;
+        }
+        median_reject(A, x, y, d, lo);
+        return;
+    }
     const int y0 = max(y - R, 0), y1 = min(y + R, A.H - 1);
     int n = 0;
     for (int yy = y0; yy <= y1; ++yy)
         for (int dx = -R; dx <= R; ++dx) {
-            int xx = x + dx;
-            xx = xx < 0 ? xx + A.W : (xx >= A.W ? xx - A.W : xx);
+            // (a window wider than the image wraps more than once)
+            const int xx = ((x + dx) % A.W + A.W) % A.W;
             n += state_depth(A, xx, yy) > 0.0f ? 1 : 0;
         }
     const int k = (n - 1) / 2;
@@ -1281,22 +1328,14 @@ __device__ __forceinline__ void median_one(const IoArgs &A, long long i)
         int c = 0;
         for (int yy = y0; yy <= y1; ++yy)
             for (int dx = -R; dx <= R; ++dx) {
-                int xx = x + dx;
-                xx = xx < 0 ? xx + A.W : (xx >= A.W ? xx - A.W : xx);
+                const int xx = ((x + dx) % A.W + A.W) % A.W;
                 const float v = state_depth(A, xx, yy);
                 c += (v > 0.0f && __float_as_uint(v) <= mid) ? 1 : 0;
             }
         if (c > k) hi = mid;
         else lo = mid + 1;
     }
-    const double m = (double)__uint_as_float(lo);
-    if (fabs((double)d - m) > A.median_rel * m) {
-        A.depth[(long long)y * A.pd + x] = 0.0f;
-        A.n0[(long long)y * A.pn0 + x] = 0.0f;
-        A.n1[(long long)y * A.pn1 + x] = 0.0f;
-        A.n2[(long long)y * A.pn2 + x] = 0.0f;
-        A.cplane[(long long)y * A.pc + x] = 2.0f;
-    }
+    median_reject(A, x, y, d, lo);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_median(Launch L)

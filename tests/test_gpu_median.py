@@ -65,3 +65,21 @@ def test_median_end_to_end(pms):
     same_removed = ((dg == 0) == (do == 0)).mean()
     print(f"{frac:.4f} within 0.5%, removal agrees at {same_removed:.4f}, kept {valid.mean():.3f}")
     assert frac >= 0.99 and same_removed >= 0.99
+
+
+@pytest.mark.parametrize("W,radius", [(24, 3), (24, 8), (6, 8)])
+def test_median_window_wider_than_a_tiny_image(pms, W, radius):
+    """Windows of up to 17 columns on keyframes 24 and 6 pixels wide: the
+    longitude wraps, more than once on the narrow one, as in the oracle."""
+    w = synth.scaled("box_room", W, seed=6)
+    params = dict(w.params, patch_size=3, patch_stride=1, iterations=0, median_radius=radius,
+                  median_rel=0.05, offsets=[(-1, 0), (1, 0), (0, -1), (0, 1)])
+    say(f"median r={radius} on {W}x{W // 2}")
+    dg, do = _run(pms, w, params)
+    band = np.zeros_like(do, dtype=bool)
+    band[1:do.shape[0] - 1] = True
+    removed_o, removed_g = band & (do == 0), band & (dg == 0)
+    print(f"removed {removed_o[band].sum()} (oracle) {removed_g[band].sum()} (gpu) of {band.sum()}")
+    assert 0 < removed_o[band].sum() < band.sum()
+    # (a depth that sits at the threshold may tip either way)
+    assert (removed_o != removed_g).sum() <= band.sum() // 100

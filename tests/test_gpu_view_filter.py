@@ -44,3 +44,20 @@ def test_counts_match_oracle_on_a_million_points(pms):
     acc_o, k_o, c_o = oracle.view_filter(ca, cb, pts)
     assert (k_g, c_g, acc_g) == (k_o, c_o, acc_o)
     assert c_o == len(pts) - 10
+
+
+def test_profiler_times_each_call(pms):
+    """The library's per-launch events time every view-filter call as one
+    entry under its own name; unknown names are refused."""
+    ctx = pms.Context(0)
+    pts = torch.zeros((1000, 3), dtype=torch.float64, device="cuda")
+    say("profiler entries of the view filter")
+    ctx.profile_enable(True)
+    for _ in range(3):
+        pms.view_filter([0.0, 0.0, 0.0], [1.0, 0.0, 0.0], pts, ctx=ctx)
+    n, ms = ctx.profile_read("view_filter")
+    assert n == 3 and ms > 0.0
+    assert ctx.profile_read("view_filter") == (0, 0.0)
+    ctx.profile_enable(False)
+    with pytest.raises(pms.PmsError):
+        ctx.profile_read("no such kernel")
