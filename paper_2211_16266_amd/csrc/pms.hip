@@ -502,6 +502,9 @@ void add_rec(Plan &P, int kind, int sub, int dtype, Variant v,
 }
 
 long long blocks_of(long long n) { return (n + pms::BLOCK - 1) / pms::BLOCK; }
+// grid of a counting kernel over n items (at least one workgroup: every
+// workgroup adds its count, zero included, after a barrier)
+unsigned count_grid(long long n) { return (unsigned)std::max(1LL, std::min(blocks_of(n), (long long)pms::COUNT_GRID)); }
 
 using GroupKey = std::tuple<int, int, int, int>;  // dtype, lpp, spl, full
 GroupKey group_key(const JobSpec &J, const Geometry &g)
@@ -1605,7 +1608,7 @@ pms_status pms_view_filter(pms_context *ctx, const double centre_a[3], const dou
         LaunchTimer timer(ctx, KK_VIEW, s);
         hipLaunchKernelGGL(pms::k_count_clear, dim3(1), dim3(64), 0, s, counts);
         if (n_points > 0)
-            hipLaunchKernelGGL(pms::k_view_filter, dim3((unsigned)blocks_of(n_points)), dim3(pms::BLOCK), 0,
+            hipLaunchKernelGGL(pms::k_view_filter, dim3(count_grid(n_points)), dim3(pms::BLOCK), 0,
                                s, centre_a[0], centre_a[1], centre_a[2], centre_b[0], centre_b[1],
                                centre_b[2], points, (long long)n_points, min_deg, max_deg, counts);
     }
@@ -1679,7 +1682,7 @@ pms_status pms_fuse(pms_context *ctx, int32_t width, int32_t height, int32_t n_m
         LaunchTimer timer(ctx, KK_FUSE, s);
         hipLaunchKernelGGL(pms::k_fuse_clear, dim3((unsigned)blocks_of((long long)cap)), dim3(pms::BLOCK), 0, s, A);
         hipLaunchKernelGGL(pms::k_fuse_insert, dim3((unsigned)blocks_of(points)), dim3(pms::BLOCK), 0, s, A);
-        hipLaunchKernelGGL(pms::k_fuse_mark, dim3((unsigned)blocks_of(points)), dim3(pms::BLOCK), 0, s, A);
+        hipLaunchKernelGGL(pms::k_fuse_mark, dim3(count_grid(points)), dim3(pms::BLOCK), 0, s, A);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(ctx, e, "fuse");
@@ -1714,7 +1717,7 @@ pms_status pms_coverage(pms_context *ctx, int32_t width, int32_t height, int32_t
         LaunchTimer timer(ctx, KK_COVER, s);
         hipLaunchKernelGGL(pms::k_cover_clear, dim3((unsigned)blocks_of(pix)), dim3(pms::BLOCK), 0, s, A);
         hipLaunchKernelGGL(pms::k_cover_mark, dim3((unsigned)blocks_of(points)), dim3(pms::BLOCK), 0, s, A);
-        hipLaunchKernelGGL(pms::k_cover_count, dim3((unsigned)blocks_of(pix)), dim3(pms::BLOCK), 0, s, A);
+        hipLaunchKernelGGL(pms::k_cover_count, dim3(count_grid(pix)), dim3(pms::BLOCK), 0, s, A);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(ctx, e, "coverage");

@@ -1565,17 +1565,49 @@ __global__ void k_count_clear(unsigned long long *counts)
     if (threadIdx.x < 2) counts[threadIdx.x] = 0ULL;
 }
 
+// Workgroups of the counting kernels, which walk their items with a grid
+// stride: one counter atomic per workgroup instead of one per wave (every
+// wave's atomic on the same address serialises; at one per wave they took
+// most of these kernels' time).
+constexpr int COUNT_GRID = 1024;
+
+// Adds the workgroup's sums of c0 and c1 to *d0 and *d1 (d1 may be null)
+// with one atomic each; every thread of the workgroup must call it.
+__device__ __forceinline__ void block_count_add(unsigned long long *d0, unsigned c0,
+                                                unsigned long long *d1, unsigned c1)
+{
+    __shared__ unsigned part[2][BLOCK / 64];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        c0 += __shfl_xor(c0, o, 64);
+        c1 += __shfl_xor(c1, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        part[0][threadIdx.x >> 6] = c0;
+        part[1][threadIdx.x >> 6] = c1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t0 = 0, t1 = 0;
+        for (int w = 0; w < BLOCK / 64; ++w) {
+            t0 += part[0][w];
+            t1 += part[1][w];
+        }
+        if (t0) atomicAdd(d0, t0);
+        if (d1 && t1) atomicAdd(d1, t1);
+    }
+}
+
 // Per sparse point the angle between the directions to the two camera
-// centres (FP64); the wave adds its counts of points in [min_deg, max_deg]
-// and of points not at a centre with one atomic each.
+// centres (FP64); counts of points in [min_deg, max_deg] and of points not
+// at a centre.
 __global__ __launch_bounds__(BLOCK) void k_view_filter(double ax, double ay, double az, double bx,
                                                        double by, double bz, const double *pts,
                                                        long long n, double min_deg, double max_deg,
                                                        unsigned long long *counts)
 {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    bool counted = false, in_range = false;
-    if (i < n) {
+    unsigned n_range = 0, n_counted = 0;
+    for (long long i = (long long)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (long long)gridDim.x * BLOCK) {
         const double px = pts[3 * i], py = pts[3 * i + 1], pz = pts[3 * i + 2];
         const double a0 = ax - px, a1 = ay - py, a2 = az - pz;
         const double b0 = bx - px, b1 = by - py, b2 = bz - pz;
@@ -1584,15 +1616,11 @@ __global__ __launch_bounds__(BLOCK) void k_view_filter(double ax, double ay, dou
             double cs = (a0 * b0 + a1 * b1 + a2 * b2) / (la * lb);
             cs = cs > 1.0 ? 1.0 : (cs < -1.0 ? -1.0 : cs);
             const double deg = acos(cs) * (180.0 / 3.14159265358979323846);
-            counted = true;
-            in_range = deg >= min_deg && deg <= max_deg;
+            n_counted += 1;
+            n_range += deg >= min_deg && deg <= max_deg ? 1 : 0;
         }
     }
-    const unsigned long long cmask = __ballot(counted), rmask = __ballot(in_range);
-    if ((threadIdx.x & 63) == 0) {
-        if (rmask) atomicAdd(&counts[0], (unsigned long long)__popcll(rmask));
-        if (cmask) atomicAdd(&counts[1], (unsigned long long)__popcll(cmask));
-    }
+    block_count_add(&counts[0], n_range, &counts[1], n_counted);
 }
 
 // ---------------------------------------------------------------------------
@@ -1692,13 +1720,13 @@ __global__ __launch_bounds__(BLOCK) void k_fuse_insert(FuseArgs A)
     }
 }
 
-// keep = this point is the first of its voxel; the wave adds its count.
+// keep = this point is the first of its voxel; the workgroup adds its count.
 __global__ __launch_bounds__(BLOCK) void k_fuse_mark(FuseArgs A)
 {
-    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long HW = (long long)A.W * A.H;
-    bool kept = false;
-    if (g < HW * A.n_maps) {
+    const long long HW = (long long)A.W * A.H, n = HW * A.n_maps;
+    unsigned n_kept = 0;
+    for (long long g = (long long)blockIdx.x * BLOCK + threadIdx.x; g < n; g += (long long)gridDim.x * BLOCK) {
+        bool kept = false;
         const int m = (int)(g / HW);
         double X[3];
         unsigned long long key;
@@ -1714,9 +1742,9 @@ __global__ __launch_bounds__(BLOCK) void k_fuse_mark(FuseArgs A)
             }
         }
         A.keep[g] = kept ? 1 : 0;
+        n_kept += kept ? 1 : 0;
     }
-    const unsigned long long bm = __ballot(kept);
-    if ((threadIdx.x & 63) == 0 && bm) atomicAdd(A.count, (unsigned long long)__popcll(bm));
+    block_count_add(A.count, n_kept, nullptr, 0);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_cover_clear(FuseArgs A)
@@ -1755,10 +1783,11 @@ __global__ __launch_bounds__(BLOCK) void k_cover_mark(FuseArgs A)
 
 __global__ __launch_bounds__(BLOCK) void k_cover_count(FuseArgs A)
 {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool c = i < (long long)A.Wc * A.Hc && A.cover[i];
-    const unsigned long long bm = __ballot(c);
-    if ((threadIdx.x & 63) == 0 && bm) atomicAdd(A.count, (unsigned long long)__popcll(bm));
+    const long long n = (long long)A.Wc * A.Hc;
+    unsigned c = 0;
+    for (long long i = (long long)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (long long)gridDim.x * BLOCK)
+        c += A.cover[i] ? 1 : 0;
+    block_count_add(A.count, c, nullptr, 0);
 }
 
 // Test hook: raw Philox blocks.

@@ -54,3 +54,14 @@ def test_committed_summary_parses():
     for r in recs:
         assert r["bytes_per_launch"] == r["fetch_bytes"] + r["write_bytes"]
         assert len(r["schedule"]) == 2 and len(r["kernel_sources"]) == 16
+
+
+def test_profile_names_are_the_librarys():
+    """The benchmark drains every per-launch timing name the library keeps,
+    so that its timed sections leave no events behind."""
+    import re
+    src = _sources()["paper_2211_16266_amd/csrc/pms.hip"]
+    block = re.search(r"kKernelNames\[kNumKernelKinds\]\s*=\s*\{(.*?)\};", src, re.S).group(1)
+    names = tuple(re.findall(r'"([a-z_]+)"', block))
+    assert names == bench.PROFILE_NAMES
+    assert set(bench.NEXT_BYTES) <= set(names)
