@@ -287,8 +287,9 @@ pms_status pms_halfsweep(pms_context *ctx, const pms_image *ref, const pms_pose 
                          pms_plane depth_io, const pms_plane normal_io[3], pms_plane cost_io,
                          void *stream);
 
-/* The geometric-consistency filter alone (Sec. III: applied once five depth
-   maps are available) on a caller-held W x H result, in place. */
+/* The geometric-consistency filter alone (Sec. III: it runs as soon as a
+   window of five keyframes has depth maps) on a caller-held W x H result,
+   in place. */
 pms_status pms_consistency(pms_context *ctx, int32_t width, int32_t height,
                            const pms_pose *ref_pose, const pms_plane *maps,
                            const pms_pose *map_poses, int32_t n_maps, const pms_params *params,

@@ -327,8 +327,9 @@ double pmsref_view_cost(int W, int H, const double *ref, const double *nbr, cons
     return 1.0 - ncc;
 }
 
-/* Several neighbours (Sec. III-C speaks of "the two neighboring frames"):
-   the mean of the k smallest view costs, k = top_k or ceil(N/2). */
+/* Several neighbours (Sec. III-C matches against the two adjacent
+   keyframes): the mean of the k smallest view costs, k = top_k or
+   ceil(N/2). */
 double pmsref_aggregate(const double *view_costs, int n_views, int top_k)
 {
     double c[PMSREF_MAX_VIEWS];
@@ -1003,9 +1004,9 @@ int pmsref_warp_planes(int W, int H, const double *src_depth, const double *src_
 }
 
 /* ------------------------------------------------------------------------ */
-/* median post-filter (Sec. III-C, item 2: a median-filtered copy of the    */
-/* depth image is compared with the original and depths deviating beyond a */
-/* threshold are removed). Window, median of an even count and the relative */
+/* median post-filter (Sec. III-C, item 2: a depth whose distance from the  */
+/* median of its window exceeds a threshold is dropped from the map).       */
+/* Window, median of an even count and the relative                         */
 /* threshold are readings. Parity: pinned by tests (flat maps, an isolated  */
 /* outlier, brute force against numpy on random maps, the seam, the exact   */
 /* threshold).                                                              */

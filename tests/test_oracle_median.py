@@ -1,6 +1,6 @@
-"""Pins of the oracle's median post-filter (Sec. III-C, item 2: a
-median-filtered copy of the depth image is compared with the original and
-depths deviating beyond a threshold are removed), against facts the oracle
+"""Pins of the oracle's median post-filter (Sec. III-C, item 2: a depth
+whose distance from the median of its window exceeds a threshold is dropped
+from the map), against facts the oracle
 does not compute itself: flat maps survive, an isolated outlier goes and its
 neighbours stay, the decision at every pixel of random maps equals a brute
 force with numpy's sort over the wrapped window, the window wraps across the
