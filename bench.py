@@ -28,7 +28,8 @@ More sections ride on the same line (skip them with --no-next /
 * "quality_3840": the 3840x1920 8-bit courtyard keyframe (6 neighbours,
   15x15 patch sampled every 2nd pixel, 10 iterations, consistency against
   4 maps of its window), timed over --quality-steps densify calls with
-  accuracy against the rendered ground truth.
+  accuracy against the rendered ground truth, then the window's 5 depth
+  maps fused into one cloud (2 cm voxels) with its panorama coverage.
 * "batch": 32 keyframe jobs (12 at 960x480, 12 at 1920x960, 8 at
   2880x1440, 3-6 neighbours each, hall generator and parameters) with
   FP16 images, as one prepared batch replayed as one HIP graph launch under
@@ -393,11 +394,27 @@ def quality_section(args, torch, pms, synth, ctx) -> dict:
     t = (time.perf_counter() - t0) / K
     r = (params["patch_size"] - 1) // 2
     comp, acc = _gt_accuracy(out[0].cpu().numpy(), w.gt_depth[w.ref], r)
+    # fusion of the window's 5 depth maps (the filtered keyframe and its 4
+    # map keyframes) into one de-duplicated cloud, and its panorama coverage
+    depths, poses = [out[0]] + maps, [rp] + map_poses
+    ctx.profile_enable(True)
+    for name in ("fuse", "coverage"):
+        ctx.profile_read(name)
+    keep, n_kept = pms.fuse(depths, poses, 0.02, ctx=ctx)
+    n_cov, _ = pms.coverage(depths, poses, keep, rp, ctx=ctx)
+    (_, fuse_ms), (_, cov_ms) = ctx.profile_read("fuse"), ctx.profile_read("coverage")
+    ctx.profile_enable(False)
+    for name in PROFILE_NAMES:
+        ctx.profile_read(name)
+    n_pts = int(sum(int((d > 0).sum().item()) for d in depths))
     return {"workload": "courtyard_3840: 3840x1920 u8, 6 neighbours, 15x15/2 (64 samples), "
-                        "10 iterations, consistency vs 4 maps",
+                        "10 iterations, consistency vs 4 maps, fusion of the window's 5 maps",
             "keyframes_per_s": 1.0 / t, "ms_per_keyframe": t * 1e3, "steps": K,
             "schedule": ctx.get_schedule(),
-            "completeness": comp, "within_1pct_of_gt": acc}
+            "completeness": comp, "within_1pct_of_gt": acc,
+            "fusion": {"maps": len(depths), "valid_points": n_pts, "voxel_m": 0.02,
+                       "kept_points": n_kept, "fuse_ms": fuse_ms, "coverage_ms": cov_ms,
+                       "covered_fraction_720x360": n_cov / (720 * 360)}}
 
 
 def batch_section(args, torch, pms, synth, pool, ctx) -> dict:
