@@ -1672,8 +1672,7 @@ pms_status pms_fuse(pms_context *ctx, int32_t width, int32_t height, int32_t n_m
     while (cap < 2ULL * (unsigned long long)points) cap <<= 1;
     if ((st = ensure_work(ctx, (size_t)cap * 2 * sizeof(unsigned long long))) != PMS_OK) return st;
     A.voxel = voxel;
-    A.keys = static_cast<unsigned long long *>(ctx->work);
-    A.vals = A.keys + cap;
+    A.slots = static_cast<unsigned long long *>(ctx->work);
     A.mask = cap - 1;
     A.keep = keep_out;
     A.count = reinterpret_cast<unsigned long long *>(n_kept_out);

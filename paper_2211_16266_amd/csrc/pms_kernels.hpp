@@ -1638,7 +1638,9 @@ struct FuseArgs {
     long long pitch[MAXV];
     ViewPoseD pose[MAXV];  // world -> camera of each map
     const double2 *tab_row64, *tab_col64;
-    unsigned long long *keys, *vals;  // hash table: voxel key, first (map, pixel)
+    // hash table of 16-byte slots: voxel key at [2h], first (map, pixel) at
+    // [2h + 1], so that a point's claim and order share one cache line
+    unsigned long long *slots;
     unsigned long long mask;          // capacity - 1 (a power of two)
     unsigned char *keep;              // n_maps x H x W
     unsigned long long *count;
@@ -1691,29 +1693,40 @@ __global__ __launch_bounds__(BLOCK) void k_fuse_clear(FuseArgs A)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i <= (long long)A.mask) {
-        A.keys[i] = EMPTY_KEY;
-        A.vals[i] = EMPTY_KEY;
+        A.slots[2 * i] = EMPTY_KEY;
+        A.slots[2 * i + 1] = EMPTY_KEY;
     }
     if (i == 0) A.count[0] = 0ULL;
 }
 
 // Each point claims its voxel's slot (linear probing; the table holds at
 // least twice as many slots as points, so a free slot is always found) and
-// lowers the slot's value to its (map, pixel) order.
+// lowers the slot's value to its (map, pixel) order. Neighbouring pixels
+// often fall into one voxel: a point whose left neighbour in the wave (the
+// order just below its own) has the same voxel leaves the claim to it, as
+// the first point of such a run carries the lowest order; this removes
+// contended atomics without changing any slot's final value.
 __global__ __launch_bounds__(BLOCK) void k_fuse_insert(FuseArgs A)
 {
     const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long HW = (long long)A.W * A.H;
-    if (g >= HW * A.n_maps) return;
-    const int m = (int)(g / HW);
-    double X[3];
-    unsigned long long key;
-    if (!fuse_point(A, m, g - (long long)m * HW, X) || !voxel_key(A, X, key)) return;
+    unsigned long long key = 0ULL;
+    bool have = false;
+    if (g < HW * A.n_maps) {
+        const int m = (int)(g / HW);
+        double X[3];
+        have = fuse_point(A, m, g - (long long)m * HW, X) && voxel_key(A, X, key);
+    }
+    const unsigned lo = (unsigned)key, hi = (unsigned)(key >> 32);
+    const unsigned left_lo = __shfl_up(lo, 1, 64), left_hi = __shfl_up(hi, 1, 64);
+    const int left_have = __shfl_up(have ? 1 : 0, 1, 64);
+    const bool run = (threadIdx.x & 63) != 0 && left_have && left_lo == lo && left_hi == hi;
+    if (!have || run) return;
     unsigned long long h = hash64(key) & A.mask;
     for (unsigned long long probe = 0; probe <= A.mask; ++probe) {
-        const unsigned long long prev = atomicCAS(&A.keys[h], EMPTY_KEY, key);
+        const unsigned long long prev = atomicCAS(&A.slots[2 * h], EMPTY_KEY, key);
         if (prev == EMPTY_KEY || prev == key) {
-            atomicMin(&A.vals[h], (unsigned long long)g);
+            atomicMin(&A.slots[2 * h + 1], (unsigned long long)g);
             return;
         }
         h = (h + 1) & A.mask;
@@ -1733,11 +1746,11 @@ __global__ __launch_bounds__(BLOCK) void k_fuse_mark(FuseArgs A)
         if (fuse_point(A, m, g - (long long)m * HW, X) && voxel_key(A, X, key)) {
             unsigned long long h = hash64(key) & A.mask;
             for (unsigned long long probe = 0; probe <= A.mask; ++probe) {
-                if (A.keys[h] == key) {
-                    kept = A.vals[h] == (unsigned long long)g;
+                if (A.slots[2 * h] == key) {
+                    kept = A.slots[2 * h + 1] == (unsigned long long)g;
                     break;
                 }
-                if (A.keys[h] == EMPTY_KEY) break;
+                if (A.slots[2 * h] == EMPTY_KEY) break;
                 h = (h + 1) & A.mask;
             }
         }
