@@ -153,12 +153,13 @@ typedef struct {
    the lanes that share one pixel. A wave of 64 lanes holds 64 /
    lanes_per_pixel pixels as wave_rows rows; a workgroup holds waves_x x
    (4 / waves_x) waves. The tile shape never changes a result;
-   lanes_per_pixel (2 or 4; 2 is used for 36-sample patches only) changes
-   the order of the patch sums and therefore the last bits of the costs. */
+   lanes_per_pixel (2, 4 or 8; 2 is used for 36-sample patches only, 8 for
+   64-sample patches only, 4 for every other patch) changes the order of
+   the patch sums and therefore the last bits of the costs. */
 typedef struct {
     int32_t wave_rows;       /* 1, 2, 4, 8 or 16; default 4 */
     int32_t waves_x;         /* 1, 2 or 4; default 2        */
-    int32_t lanes_per_pixel; /* 2 or 4; default 4           */
+    int32_t lanes_per_pixel; /* 2, 4 or 8; default 4        */
 } pms_schedule;
 
 typedef struct pms_batch pms_batch;
@@ -227,7 +228,7 @@ pms_status pms_get_schedule(const pms_context *ctx, pms_schedule *out);
 pms_status pms_set_schedule(pms_context *ctx, const pms_schedule *s);
 
 /* Autotuner: densifies the jobs (as one batch) under every tile shape (and,
-   with try_lanes != 0, both lanes_per_pixel values), timing the
+   with try_lanes != 0, every lanes_per_pixel value), timing the
    initialisation and half-sweep kernels over `reps` runs after one warm-up,
    and leaves the fastest schedule set on the context. Synchronous; the
    jobs' output planes receive the last run's results. */

@@ -62,7 +62,8 @@ struct Staging {
 struct Schedule {
     int wy_log2 = 2;  // a wave covers 2^wy_log2 pixel rows
     int bx_log2 = 1;  // a workgroup holds 2^bx_log2 waves side by side
-    int lpp = 0;      // lanes per pixel for 36-sample patches (0: 4)
+    int lpp = 0;      // lanes per pixel: 2 for 36-sample patches, 8 for
+                      // 64-sample ones, 0 for 4 everywhere
 };
 
 }  // namespace
@@ -391,6 +392,7 @@ struct Variant {
 Variant pick_variant(int P, const Schedule &sc)
 {
     if (P == 36 && sc.lpp == 2) return {2, 18, true};
+    if (P == 64 && sc.lpp == 8) return {8, 8, true};
     if (P % 4 == 0 && (P / 4 == 9 || P / 4 == 16)) return {4, P / 4, true};
     const int need = (P + 3) / 4;
     return {4, need <= 4 ? 4 : need <= 9 ? 9 : need <= 13 ? 13 : 16, false};
@@ -870,6 +872,7 @@ void launch_tiles_dt(const Variant &v, const pms::Launch &L, dim3 grid, hipStrea
 {
     using namespace pms;
     if (v.lpp == 2) hipLaunchKernelGGL((k_tiles<KIND, DT, 2, 18, true>), grid, dim3(BLOCK), 0, s, L);
+    else if (v.lpp == 8) hipLaunchKernelGGL((k_tiles<KIND, DT, 8, 8, true>), grid, dim3(BLOCK), 0, s, L);
     else if (v.full && v.spl == 9) hipLaunchKernelGGL((k_tiles<KIND, DT, 4, 9, true>), grid, dim3(BLOCK), 0, s, L);
     else if (v.full && v.spl == 16) hipLaunchKernelGGL((k_tiles<KIND, DT, 4, 16, true>), grid, dim3(BLOCK), 0, s, L);
     else if (v.spl == 4) hipLaunchKernelGGL((k_tiles<KIND, DT, 4, 4, false>), grid, dim3(BLOCK), 0, s, L);
@@ -1189,7 +1192,7 @@ pms_status pms_get_schedule(const pms_context *ctx, pms_schedule *out)
     if (!ctx || !out) return PMS_ERR_INVALID_ARG;
     out->wave_rows = 1 << ctx->sched.wy_log2;
     out->waves_x = 1 << ctx->sched.bx_log2;
-    out->lanes_per_pixel = ctx->sched.lpp == 2 ? 2 : 4;
+    out->lanes_per_pixel = ctx->sched.lpp == 0 ? 4 : ctx->sched.lpp;
     return PMS_OK;
 }
 
@@ -1202,11 +1205,11 @@ pms_status pms_set_schedule(pms_context *ctx, const pms_schedule *s)
         return fail(ctx, PMS_ERR_INVALID_ARG, "wave_rows must be 1, 2, 4, 8 or 16");
     if (!pow2(s->waves_x) || s->waves_x > 4)
         return fail(ctx, PMS_ERR_INVALID_ARG, "waves_x must be 1, 2 or 4");
-    if (s->lanes_per_pixel != 2 && s->lanes_per_pixel != 4)
-        return fail(ctx, PMS_ERR_INVALID_ARG, "lanes_per_pixel must be 2 or 4");
+    if (s->lanes_per_pixel != 2 && s->lanes_per_pixel != 4 && s->lanes_per_pixel != 8)
+        return fail(ctx, PMS_ERR_INVALID_ARG, "lanes_per_pixel must be 2, 4 or 8");
     ctx->sched.wy_log2 = ilog2(s->wave_rows);
     ctx->sched.bx_log2 = ilog2(s->waves_x);
-    ctx->sched.lpp = s->lanes_per_pixel == 2 ? 2 : 0;
+    ctx->sched.lpp = s->lanes_per_pixel == 4 ? 0 : s->lanes_per_pixel;
     return PMS_OK;
 }
 
@@ -1362,8 +1365,8 @@ pms_status pms_autotune(pms_context *ctx, const pms_job *jobs, int32_t n_jobs, i
     earlier.swap(ctx->launches);
     double best = 1e300;
     Schedule best_s = keep;
-    const int lanes[2] = {0, 2};
-    for (int li = 0; li < (try_lanes ? 2 : 1); ++li)
+    const int lanes[3] = {0, 2, 8};
+    for (int li = 0; li < (try_lanes ? 3 : 1); ++li)
         for (int wy = 0; wy <= 4; ++wy)
             for (int bx = 0; bx <= 2; ++bx) {
                 Schedule c;

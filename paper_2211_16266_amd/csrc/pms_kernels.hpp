@@ -2,12 +2,13 @@
 // densification (Surmann et al., Sec. III-B/C). Included once, by pms.hip.
 //
 // Work decomposition
-//   * One reference pixel is served by LPP (2 or 4) adjacent lanes of a
-//     wave64 inside one DPP quad. Each lane owns every LPP-th patch sample:
-//     its bearing, its centred reference value and, per view, its warped
-//     neighbour value stay in VGPRs; patch sums are reduced inside the group
-//     with quad_perm DPP adds, so the reduction order depends on the patch
-//     only. LPP is chosen from the patch size alone.
+//   * One reference pixel is served by LPP (2, 4 or 8) adjacent lanes of a
+//     wave64 inside one half row of 8 lanes. Each lane owns every LPP-th
+//     patch sample: its bearing, its centred reference value and, per view,
+//     its warped neighbour value stay in VGPRs; patch sums are reduced
+//     inside the group with DPP adds (quad_perm, then row_half_mirror for 8
+//     lanes), so the reduction order depends on the patch and the context's
+//     schedule only, never on the launch.
 //   * A workgroup of 256 threads covers a (32/LPP) x 8 tile of pixels of one
 //     colour (red-black sweep) or of all pixels (init / cost evaluation); tiles are
 //     handed out so that each XCD walks a contiguous band of rows and keeps
@@ -163,14 +164,17 @@ struct Storage<DT_U8> {
 // small helpers
 // ---------------------------------------------------------------------------
 
-// Sum over the LPP lanes of a pixel: quad_perm [1,0,3,2], then (LPP = 4)
-// [2,3,0,1]. Every lane of the group ends with the same bits
-// ((a+b)+(c+d) == (b+a)+(d+c) exactly).
+// Sum over the LPP lanes of a pixel: quad_perm [1,0,3,2], then (LPP >= 4)
+// [2,3,0,1], then (LPP = 8) row_half_mirror, which pairs each lane of one
+// quad with a lane of the other quad of its 8. Every lane of the group
+// ends with the same bits ((a+b)+(c+d) == (b+a)+(d+c) exactly, and the
+// last step adds the two quads' equal sums in either order).
 template <int LPP>
 __device__ __forceinline__ float group_sum(float v)
 {
     v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, true));
-    if (LPP == 4) v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, true));
+    if (LPP >= 4) v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, true));
+    if (LPP == 8) v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x141, 0xF, 0xF, true));
     return v;
 }
 
@@ -178,7 +182,8 @@ template <int LPP>
 __device__ __forceinline__ int group_and(int v)
 {
     v &= __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true);
-    if (LPP == 4) v &= __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true);
+    if (LPP >= 4) v &= __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true);
+    if (LPP == 8) v &= __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true);
     return v;
 }
 

@@ -244,11 +244,12 @@ def test_schedule_round_trip_and_rejection(B, vctx):
     sc = B.Schedule()
     assert L.pms_get_schedule(vctx, C.byref(sc)) == OK
     assert (sc.wave_rows, sc.waves_x, sc.lanes_per_pixel) == (4, 2, 4)
-    for bad in [(3, 2, 4), (32, 2, 4), (4, 8, 4), (4, 3, 4), (4, 2, 1), (0, 2, 4)]:
+    for bad in [(3, 2, 4), (32, 2, 4), (4, 8, 4), (4, 3, 4), (4, 2, 1), (0, 2, 4), (4, 2, 3), (4, 2, 16)]:
         assert L.pms_set_schedule(vctx, C.byref(B.Schedule(*bad))) == INVALID
-    assert L.pms_set_schedule(vctx, C.byref(B.Schedule(16, 1, 2))) == OK
-    assert L.pms_get_schedule(vctx, C.byref(sc)) == OK
-    assert (sc.wave_rows, sc.waves_x, sc.lanes_per_pixel) == (16, 1, 2)
+    for good in [(16, 1, 2), (8, 1, 8), (4, 2, 4)]:
+        assert L.pms_set_schedule(vctx, C.byref(B.Schedule(*good))) == OK
+        assert L.pms_get_schedule(vctx, C.byref(sc)) == OK
+        assert (sc.wave_rows, sc.waves_x, sc.lanes_per_pixel) == good
 
 
 def test_server_entry_points_validate(B, vctx):

@@ -288,6 +288,45 @@ def test_densify_end_to_end_matches_oracle(pms, name, iters):
     assert np.all(dg[:r] == 0) and np.all(cg[:r] == 2.0) and np.all(ng[:, :r] == 0)
 
 
+@pytest.mark.parametrize("name,lanes", [("hall384", 2), ("court320_u8", 8)])
+def test_lane_variants_match_oracle(pms, name, lanes):
+    """The 2- and 8-lanes-per-pixel variants (for 36- and 64-sample patches,
+    chosen by the context's schedule) against the oracle: per-view costs on
+    identical hypotheses within 1e-4, end-to-end depth within 0.5% at >= 99%
+    of oracle-valid pixels, and no tile shape changes their results."""
+    w = _workload(name)
+    params = dict(w.params, iterations=3)
+    imgs = gpu_images(w)
+    ref, nbrs = split(w, imgs)
+    rp, nps = _poses(w)
+    ctx = pms.Context(0)
+    ctx.set_schedule(wave_rows=8, waves_x=1, lanes_per_pixel=lanes)
+    assert ctx.get_schedule()["lanes_per_pixel"] == lanes
+    d, n = random_hypotheses(w, seed=5)
+    say(f"eval_cost {name} with {lanes} lanes per pixel")
+    _, pv_g = pms.eval_cost(ref, nbrs, rp, nps, params, _t(d), _t(n), per_view=True, ctx=ctx)
+    torch.cuda.synchronize()
+    pv_g = pv_g.cpu().numpy().astype(np.float64)
+    imgs64 = _oracle_view_images(w)
+    r64, n64 = split(w, imgs64)
+    _, pv_o = oracle.eval_cost(r64, n64, rp, nps, params, d.astype(np.float64), n.astype(np.float64))
+    mx, p999 = _compare_view_costs(w, imgs64, d, n, pv_g, pv_o, params)
+    say(f"densify {name} with {lanes} lanes per pixel, two tile shapes")
+    dg = pms.densify(ref, nbrs, rp, nps, params, ctx=ctx)[0]
+    ctx.set_schedule(wave_rows=2, waves_x=2, lanes_per_pixel=lanes)
+    dg2 = pms.densify(ref, nbrs, rp, nps, params, ctx=ctx)[0]
+    torch.cuda.synchronize()
+    dg, dg2 = dg.cpu().numpy(), dg2.cpu().numpy()
+    assert np.array_equal(dg, dg2)
+    do = oracle.densify(r64, n64, rp, nps, params)[0]
+    valid = do > 0
+    frac = (np.abs(dg[valid] - do[valid]) <= 0.005 * do[valid]).mean()
+    print(f"{name}, {lanes} lanes: per-view |diff| max {mx:.2e} p99.9 {p999:.2e}; "
+          f"{frac:.4f} of oracle-valid pixels within 0.5%")
+    assert frac >= 0.99
+    ctx.close()
+
+
 def test_densify_iterations_zero_is_the_random_init(pms):
     w = _workload("box256")
     params = dict(w.params, iterations=0, seed=42)
