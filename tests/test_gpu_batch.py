@@ -244,3 +244,30 @@ def test_full_size_mixed_batch_sampled(pms):
         assert within > 0.5
     batch.close()
     ctx.close()
+
+
+def test_autotune_over_lanes_keeps_solo_results(pms):
+    """With try_lanes the autotuner also times 2 and 8 lanes per pixel; a
+    36-sample and a 64-sample job then give, under the schedule it leaves,
+    their solo results bit for bit."""
+    ctx = pms.Context(0)
+    hall = _hall(192, 0, False)
+    court = synth.scaled("courtyard", 192, seed=1)
+    jobs = []
+    for w in (hall, court):
+        imgs = _tensors(w)
+        jobs.append(pms.job(imgs[w.ref], [imgs[i] for i in w.nbrs], w.poses[w.ref],
+                            [w.poses[i] for i in w.nbrs], dict(w.params, iterations=2)))
+    say("autotune over tile shapes and lanes per pixel")
+    best, ms = ctx.autotune(jobs, reps=1, try_lanes=True)
+    assert ms > 0 and best["lanes_per_pixel"] in (2, 4, 8)
+    assert ctx.get_schedule() == best
+    # (the outputs hold the last schedule tried; run the batch under the
+    # schedule left on the context)
+    say(f"batch and solo runs under {best}")
+    pms.densify_batch(jobs, ctx=ctx)
+    torch.cuda.synchronize()
+    tuned = [tuple(t.clone() for t in jd.out) for jd in jobs]
+    for k, jd in enumerate(jobs):
+        assert _same(_alone(pms, jd, ctx), tuned[k]), f"job {k} differs from its solo run"
+    ctx.close()
