@@ -110,6 +110,8 @@ def lib() -> C.CDLL:
                                             C.POINTER(Pose), C.POINTER(Pose), C.POINTER(Params),
                                             _D, _D, _D, C.c_int, C.c_int, C.c_int, C.c_int,
                                             _D, _D, _D, C.c_int]
+        L.pmsref_set_decision_noise.argtypes = [C.c_double]
+        L.pmsref_set_decision_noise.restype = None
         L.pmsref_pixel_valid.argtypes = [C.c_int, C.c_int, C.POINTER(Params), C.c_int, C.c_int]
         _U8 = C.POINTER(C.c_uint8)
         L.pmsref_fuse.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(_D), C.POINTER(Pose), C.c_double,
@@ -401,6 +403,15 @@ def densify(ref, nbrs, ref_pose, nbr_poses, params: dict, init_depth=None, init_
     if rc:
         raise ValueError(f"pmsref_densify failed: {rc}")
     return depth, normal, cost
+
+
+def set_decision_noise(amplitude: float) -> None:
+    """Study hook, off (0) by default: adds a deterministic offset uniform in
+    [-amplitude, amplitude] to every cost that enters an accept decision
+    (initial costs, propagation and refinement candidates). Used only to
+    measure how far the oracle moves under independent per-evaluation
+    errors; see ``pmsref.h``."""
+    lib().pmsref_set_decision_noise(float(amplitude))
 
 
 def warp_planes(src_depth, src_normal, src_pose, dst_pose, params: dict):

@@ -516,6 +516,31 @@ static void random_plane(const job_t *J, int x, int y, double *d, double n[3])
 /* red-black update of one pixel (Sec. III-C)                               */
 /* ------------------------------------------------------------------------ */
 
+/* Decision-noise study hook (see pmsref.h): off unless set. The offset of
+   (pixel, iteration, slot) is splitmix64 of a key made of the three, mapped
+   to [-a, a]; slot 0 is the initial cost, 1 + k propagation candidate k,
+   1 + PMSREF_MAX_OFFSETS + k refinement trial k. */
+static double g_decision_noise = 0.0;
+
+void pmsref_set_decision_noise(double amplitude) { g_decision_noise = amplitude; }
+
+static uint64_t mix64(uint64_t z)
+{
+    z += 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+static double with_noise(double c, long pixel, int iteration, int slot)
+{
+    if (g_decision_noise <= 0.0 || !(c < 2.0)) return c;
+    uint64_t k = mix64((uint64_t)pixel);
+    k = mix64(k ^ ((uint64_t)iteration << 32 | (uint64_t)(uint32_t)slot));
+    double u = (double)(k >> 11) * (1.0 / 9007199254740992.0); /* [0, 1) */
+    return c + g_decision_noise * (2.0 * u - 1.0);
+}
+
 static void update_one(const job_t *J, const double *depth, const double *normal,
                        const double *cost, int iteration, int x, int y, double *d_out,
                        double n_out[3], double *c_out)
@@ -549,7 +574,7 @@ static void update_one(const job_t *J, const double *depth, const double *normal
         if (!(den < 0.0)) continue;
         double dd = cq / den;
         if (!(dd >= p->depth_min && dd <= p->depth_max)) continue;
-        double c = hyp_cost(J, x, y, dd, nq, NULL);
+        double c = with_noise(hyp_cost(J, x, y, dd, nq, NULL), i, iteration, 1 + k);
         if (c < best_c) {
             best_c = c;
             best_d = dd;
@@ -580,7 +605,8 @@ static void update_one(const job_t *J, const double *depth, const double *normal
         nn[1] /= len;
         nn[2] /= len;
         if (!(dot3(nn, bp) < 0.0)) continue;
-        double c = hyp_cost(J, x, y, dd, nn, NULL);
+        double c = with_noise(hyp_cost(J, x, y, dd, nn, NULL), i, iteration,
+                              1 + PMSREF_MAX_OFFSETS + k);
         if (c < best_c) {
             best_c = c;
             best_d = dd;
@@ -761,7 +787,7 @@ static void init_range(void *vctx, long begin, long end)
         C->normal[i] = n[0];
         C->normal[HW + i] = n[1];
         C->normal[2 * HW + i] = n[2];
-        C->cost[i] = hyp_cost(J, x, y, d, n, NULL);
+        C->cost[i] = with_noise(hyp_cost(J, x, y, d, n, NULL), i, 0, 0);
     }
 }
 

@@ -140,6 +140,19 @@ int pmsref_halfsweep_rows(int W, int H, const double *ref, int n_views,
                           int y1, double *depth_out, double *normal_out,
                           double *cost_out, int n_threads);
 
+/* --- decision-noise study hook (off by default) -----------------------------
+   With amplitude a > 0, every matching cost that takes part in an accept
+   decision -- the initial cost of a pixel and each propagation and
+   refinement candidate's cost in a half-sweep -- has a deterministic
+   pseudo-random offset, uniform in [-a, a] and keyed on (pixel, iteration,
+   candidate slot), added before it is compared or stored (invalid costs of
+   2 are left alone). It models an implementation whose cost evaluations
+   carry independent rounding errors of up to a, so that the oracle's own
+   sensitivity to such errors can be measured. a = 0, the default, leaves
+   every result exactly as described above. Process-wide; set it only while
+   no other call runs. */
+void pmsref_set_decision_noise(double amplitude);
+
 /* --- geometric consistency ------------------------------------------------
    Filters (depth, normal, cost) of the reference in place against n_maps
    depth maps of other keyframes. If err_px/err_depth/agree are non-null they
