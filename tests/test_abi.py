@@ -309,3 +309,35 @@ def test_fusion_entry_points_validate(B, vctx):
                           None) == DEVICE
     assert L.pms_coverage(vctx, W, H, 2, maps, poses, None, C.byref(c.pose), 720, 300, cov, cnt,
                           None) == INVALID
+
+
+def test_struct_offsets_match_the_compiled_header(B, tmp_path):
+    """Every field offset and struct size of the binding's ctypes structs
+    equals what a C compiler makes of include/pms.h (gcc, host ABI)."""
+    import shutil
+    import subprocess
+    if not shutil.which("gcc"):
+        pytest.skip("no C compiler")
+    structs = {"pms_image": B.Image, "pms_plane": B.Plane, "pms_pose": B.Pose,
+               "pms_params": B.Params, "pms_job": B.Job, "pms_schedule": B.Schedule}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "pms.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'  printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for ln in out:
+        if ln:
+            cname, field, val = ln.split()
+            got[(cname, field)] = int(val)
+    for cname, cls in structs.items():
+        assert got[(cname, "sizeof")] == C.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
