@@ -198,6 +198,34 @@ pms_status pms_densify(pms_context *ctx, const pms_image *ref, const pms_pose *r
                        const pms_params *params, pms_plane depth_out,
                        const pms_plane normal_out[3], pms_plane cost_out, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the same
+   arguments, validation and results as pms_densify, but the call's working
+   memory -- bearing tables, argument tables, plane state, patch statistics
+   and the re-laid-out neighbour images -- lives in a fixed scratch array of
+   PMS_NOALLOC_SCRATCH_BYTES compiled into the library. Each GPU the library
+   runs on holds its own copy until the process ends; its address is looked
+   up once per device by pms_context_create. The call makes no device or
+   pinned-host allocation (no hipMalloc, hipFree, hipHostMalloc or stream-
+   ordered allocation) and records no profiling events; it uploads its
+   tables with one copy from a pageable host buffer of the context, and only
+   the host-side plan bookkeeping uses ordinary heap containers.
+   Limit: returns PMS_ERR_BUDGET, enqueuing nothing, when the call needs
+   more than PMS_NOALLOC_SCRATCH_BYTES (about 24 B x (W + H) of tables plus
+   28 B per pixel of state plus the neighbour copies: e.g. 960 x 480 with up
+   to 6 neighbours fits). Every call on one GPU shares that GPU's array and
+   leaves its contents behind (nothing in it needs clearing: each call
+   writes every scratch word it reads): calls that can run at the same time
+   on one GPU -- on different streams, or from different contexts or
+   threads without ordering -- race and give undefined results; calls
+   enqueued on one stream are ordered and safe. */
+#define PMS_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+pms_status pms_densify_noalloc(pms_context *ctx, const pms_image *ref, const pms_pose *ref_pose,
+                               const pms_image *nbrs, const pms_pose *nbr_poses, int32_t n_nbrs,
+                               const pms_plane *maps, const pms_pose *map_poses, int32_t n_maps,
+                               const pms_params *params, pms_plane depth_out,
+                               const pms_plane normal_out[3], pms_plane cost_out, void *stream);
+
 /* Densifies n_jobs (1 .. PMS_MAX_BATCH) keyframes of any mix of sizes,
    neighbour counts and parameters together: every step of the method runs
    as one launch over the tiles of all jobs still at that step, so small

@@ -13,5 +13,5 @@ import torch  # noqa: F401  (load torch's HIP runtime before libpms)
 
 from ._binding import (LIB_PATH, coverage, fuse, MAX_BATCH, MAX_MAPS, MAX_VIEWS, Batch, Context,  # noqa: F401
                        JobDesc, PmsError, Server, consistency, default_context, default_params, densify,
-                       densify_batch, densify_job, eval_cost, halfsweep, job, lib,
+                       densify_batch, densify_job, densify_noalloc, eval_cost, halfsweep, job, lib,
                        philox_stream, view_filter, warp_planes)

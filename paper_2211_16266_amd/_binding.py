@@ -15,6 +15,7 @@ import torch
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libpms.so")
 
+NOALLOC_SCRATCH_BYTES = 128 << 20  # PMS_NOALLOC_SCRATCH_BYTES of pms.h
 MAX_VIEWS = 8
 MAX_MAPS = 8
 MAX_OFFSETS = 16
@@ -91,6 +92,7 @@ def lib() -> C.CDLL:
         L.pms_densify.argtypes = [C.c_void_p, P(Image), P(Pose), P(Image), P(Pose), C.c_int32,
                                   P(Plane), P(Pose), C.c_int32, P(Params), Plane, P(Plane), Plane,
                                   C.c_void_p]
+        L.pms_densify_noalloc.argtypes = L.pms_densify.argtypes
         L.pms_eval_cost.argtypes = [C.c_void_p, P(Image), P(Pose), P(Image), P(Pose), C.c_int32,
                                     P(Params), Plane, P(Plane), Plane, P(Plane), C.c_void_p]
         L.pms_halfsweep.argtypes = [C.c_void_p, P(Image), P(Pose), P(Image), P(Pose), C.c_int32,
@@ -132,7 +134,7 @@ def lib() -> C.CDLL:
         L.pms_last_error.argtypes = [C.c_void_p]
         L.pms_last_error.restype = C.c_char_p
         for name in ("pms_default_params", "pms_context_create", "pms_context_destroy",
-                     "pms_densify", "pms_eval_cost", "pms_halfsweep", "pms_consistency",
+                     "pms_densify", "pms_densify_noalloc", "pms_eval_cost", "pms_halfsweep", "pms_consistency",
                      "pms_philox_stream", "pms_profile_enable", "pms_profile_read",
                      "pms_densify_batch", "pms_batch_create", "pms_batch_run", "pms_batch_bytes",
                      "pms_batch_destroy", "pms_get_schedule", "pms_set_schedule", "pms_autotune",
@@ -311,6 +313,22 @@ def densify(ref: torch.Tensor, nbrs, ref_pose, nbr_poses, params: dict | None = 
     """Depth (H, W), normal (3, H, W) and cost (H, W) float32 device tensors
     of the reference keyframe. ``maps``/``map_poses`` enable the consistency
     filter. ``out`` may supply the three output tensors."""
+    return _densify_call("pms_densify", ref, nbrs, ref_pose, nbr_poses, params, maps, map_poses,
+                         out, ctx, stream)
+
+
+def densify_noalloc(ref: torch.Tensor, nbrs, ref_pose, nbr_poses, params: dict | None = None,
+                    maps=None, map_poses=None, out=None, ctx: Context | None = None, stream=None):
+    """``densify`` through ``pms_densify_noalloc``: the library's working
+    memory comes from its fixed per-device scratch array. Pass ``out`` to
+    make the call itself allocate nothing (otherwise the three output
+    tensors are allocated here, by torch, before the call)."""
+    return _densify_call("pms_densify_noalloc", ref, nbrs, ref_pose, nbr_poses, params, maps,
+                         map_poses, out, ctx, stream)
+
+
+def _densify_call(fn: str, ref, nbrs, ref_pose, nbr_poses, params, maps, map_poses, out, ctx,
+                  stream):
     ctx = ctx or default_context(ref.device.index or 0)
     H, W = ref.shape
     if out is None:
@@ -324,13 +342,13 @@ def densify(ref: torch.Tensor, nbrs, ref_pose, nbr_poses, params: dict | None = 
     if len(maps) != len(map_poses):
         raise ValueError("maps and map_poses differ in length")
     mp = (Plane * max(1, len(maps)))(*[make_plane(m, "map") for m in maps])
-    st = lib().pms_densify(ctx.handle, C.byref(make_image(ref, "ref")), C.byref(make_pose(ref_pose)),
-                           _views(nbrs), _poses(nbr_poses), len(nbrs),
-                           mp if maps else None, _poses(map_poses) if maps else None, len(maps),
-                           C.byref(make_params(params)), make_plane(depth, "depth"),
-                           _planes3(normal, "normal"), make_plane(cost, "cost"),
-                           C.c_void_p(_stream_handle(stream)))
-    ctx.check(st, "pms_densify")
+    st = getattr(lib(), fn)(ctx.handle, C.byref(make_image(ref, "ref")), C.byref(make_pose(ref_pose)),
+                            _views(nbrs), _poses(nbr_poses), len(nbrs),
+                            mp if maps else None, _poses(map_poses) if maps else None, len(maps),
+                            C.byref(make_params(params)), make_plane(depth, "depth"),
+                            _planes3(normal, "normal"), make_plane(cost, "cost"),
+                            C.c_void_p(_stream_handle(stream)))
+    ctx.check(st, fn)
     return depth, normal, cost
 
 

@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <tuple>
@@ -83,6 +84,7 @@ struct pms_context {
     bool capturing = false;
     std::string last_error;
     bool profiling = false;
+    std::vector<char> noalloc_host;  // pageable upload buffer of pms_densify_noalloc
     std::vector<TimedLaunch> launches;
     std::vector<hipEvent_t> event_pool;
 };
@@ -302,19 +304,15 @@ pms_status set_device(pms_context *ctx)
     return PMS_OK;
 }
 
-// Bearing tables of a W x H image (per row sin/cos of the latitude, per
-// column sin/cos of the longitude, FP64 and rounded to FP32), computed on
-// the host once per size and kept for the context's lifetime.
-pms_status get_tables(pms_context *ctx, int W, int H, Tables *out)
+// Bearing tables of a W x H image: per row sin/cos of the latitude, per
+// column sin/cos of the longitude, FP64 and rounded to FP32, laid out as
+// [row f32 | col f32 | row f64 | col f64].
+size_t tables_bytes(int W, int H) { return ((size_t)W + H) * (sizeof(float2) + sizeof(double2)); }
+
+void fill_tables_host(int W, int H, char *host)
 {
-    auto it = ctx->tables.find({W, H});
-    if (it != ctx->tables.end()) {
-        *out = it->second;
-        return PMS_OK;
-    }
     const size_t n = (size_t)W + H;
-    std::vector<char> host(n * (sizeof(float2) + sizeof(double2)));
-    float2 *row = reinterpret_cast<float2 *>(host.data());
+    float2 *row = reinterpret_cast<float2 *>(host);
     float2 *col = row + H;
     double2 *row64 = reinterpret_cast<double2 *>(row + n);
     double2 *col64 = row64 + H;
@@ -329,6 +327,31 @@ pms_status get_tables(pms_context *ctx, int W, int H, Tables *out)
         col64[i] = make_double2(std::sin(lam), std::cos(lam));
         col[i] = make_float2((float)col64[i].x, (float)col64[i].y);
     }
+}
+
+// The table pointers of a block laid out by fill_tables_host at `dev`.
+Tables tables_at(void *dev, int W, int H)
+{
+    const size_t n = (size_t)W + H;
+    Tables t;
+    t.row = static_cast<float2 *>(dev);
+    t.col = t.row + H;
+    t.row64 = reinterpret_cast<double2 *>(t.row + n);
+    t.col64 = t.row64 + H;
+    return t;
+}
+
+// Bearing tables computed on the host once per size and kept for the
+// context's lifetime.
+pms_status get_tables(pms_context *ctx, int W, int H, Tables *out)
+{
+    auto it = ctx->tables.find({W, H});
+    if (it != ctx->tables.end()) {
+        *out = it->second;
+        return PMS_OK;
+    }
+    std::vector<char> host(tables_bytes(W, H));
+    fill_tables_host(W, H, host.data());
     void *dev = nullptr;
     hipError_t e = hipMalloc(&dev, host.size());
     if (e != hipSuccess) return fail(ctx, PMS_ERR_OUT_OF_MEMORY, "hipMalloc of bearing tables failed");
@@ -337,11 +360,7 @@ pms_status get_tables(pms_context *ctx, int W, int H, Tables *out)
         (void)hipFree(dev);
         return hip_fail(ctx, e, "bearing table upload");
     }
-    Tables t;
-    t.row = static_cast<float2 *>(dev);
-    t.col = t.row + H;
-    t.row64 = reinterpret_cast<double2 *>(t.row + n);
-    t.col64 = t.row64 + H;
+    const Tables t = tables_at(dev, W, H);
     ctx->tables[{W, H}] = t;
     *out = t;
     return PMS_OK;
@@ -366,7 +385,7 @@ struct LaunchTimer {
     hipEvent_t a = nullptr, b = nullptr;
     LaunchTimer(pms_context *c, int k, hipStream_t s) : ctx(c), kind(k), stream(s)
     {
-        if (ctx->profiling && !ctx->capturing) {
+        if (kind >= 0 && ctx->profiling && !ctx->capturing) {
             a = take_event(ctx);
             b = take_event(ctx);
             if (a) (void)hipEventRecord(a, stream);
@@ -645,16 +664,22 @@ void fill_geo(pms::GeoArgs &G, const JobSpec &J, int r, const Tables &T)
 
 // Builds the plan of `specs`. With base == nullptr only sizes and launches
 // are final (used to size the device block); with the block's address every
-// pointer in the tables is final too.
-pms_status build_plan(pms_context *ctx, const std::vector<JobSpec> &specs, char *base, Plan &P)
+// pointer in the tables is final too. `fixed` (all jobs of one size) names
+// bearing tables the caller placed itself instead of the context's.
+pms_status build_plan(pms_context *ctx, const std::vector<JobSpec> &specs, char *base, Plan &P,
+                      const Tables *fixed = nullptr)
 {
     P = Plan();
     const int n = (int)specs.size();
     std::vector<Geometry> geo(n);
     std::vector<Tables> tabs(n);
     for (int i = 0; i < n; ++i) {
-        pms_status st = get_tables(ctx, specs[i].W, specs[i].H, &tabs[i]);
-        if (st != PMS_OK) return st;
+        if (fixed) {
+            tabs[i] = *fixed;
+        } else {
+            pms_status st = get_tables(ctx, specs[i].W, specs[i].H, &tabs[i]);
+            if (st != PMS_OK) return st;
+        }
         if (specs[i].mode != MODE_GEO) geo[i] = geometry(specs[i], ctx->sched);
         else geo[i].r = (specs[i].p->patch_size - 1) / 2;
     }
@@ -889,11 +914,12 @@ void launch_tiles(int dtype, const Variant &v, const pms::Launch &L, dim3 grid, 
     else launch_tiles_dt<KIND, pms::DT_U8>(v, L, grid, s);
 }
 
-// Enqueues every launch of a plan whose tables sit at `dev`.
-pms_status enqueue_plan(pms_context *ctx, const Plan &P, char *dev, hipStream_t s)
+// Enqueues every launch of a plan whose tables sit at `dev`; `timed` = false
+// records no profiling events even when the context profiles.
+pms_status enqueue_plan(pms_context *ctx, const Plan &P, char *dev, hipStream_t s, bool timed = true)
 {
     for (const Rec &R : P.recs) {
-        LaunchTimer timer(ctx, R.kind, s);
+        LaunchTimer timer(ctx, timed ? R.kind : -1, s);
         if (R.kind == KK_IO && R.sub != IO_PAD) {
             const pms::IoArgs &io = P.jobs[R.job].io;
             dim3 grid((unsigned)blocks_of((long long)io.W * io.H));
@@ -960,6 +986,81 @@ pms_status run_specs(pms_context *ctx, const std::vector<JobSpec> &specs, hipStr
     if ((st = build_plan(ctx, specs, base, P)) != PMS_OK) return st;
     if ((st = upload_args(ctx, P, base, s)) != PMS_OK) return st;
     return enqueue_plan(ctx, P, base, s);
+}
+
+// ---------------------------------------------------------------------------
+// Fixed scratch of pms_densify_noalloc: one array per GPU, compiled into the
+// library. Host code must never pass `scratch` itself to a kernel or a copy
+// (in host code it names a host-side stand-in); it uses the device address
+// hipGetSymbolAddress returned for the current device, kept in
+// g_scratch_ptr. Layout of one call: [bearing tables | plan block].
+// ---------------------------------------------------------------------------
+
+static __device__ __align__(256) unsigned char scratch[PMS_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+bool g_scratch_done[kMaxDevices] = {};
+
+// Looks up this device's copy of the scratch array once per device, with
+// the device current. Called at context creation.
+void scratch_setup(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_done[device]) return;
+    int prev = 0;
+    hipError_t e = hipGetDevice(&prev);
+    if (e == hipSuccess) e = hipSetDevice(device);
+    void *ptr = nullptr;
+    if (e == hipSuccess) e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e == hipSuccess && !ptr) e = hipErrorInvalidSymbol;
+    (void)hipSetDevice(prev);
+    g_scratch_ptr[device] = e == hipSuccess ? ptr : nullptr;
+    g_scratch_err[device] = e;
+    g_scratch_done[device] = true;
+}
+
+// Runs one validated job through the device's scratch array: no device or
+// pinned-host allocation. The argument and bearing tables go up in one copy
+// from the context's pageable host buffer (HIP stages a pageable source
+// before the call returns, so the buffer may be rewritten by the next call).
+pms_status run_noalloc(pms_context *ctx, const std::vector<JobSpec> &specs, hipStream_t s)
+{
+    pms_status st = set_device(ctx);
+    if (st != PMS_OK) return st;
+    const int dev = ctx->device;
+    void *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (dev >= kMaxDevices || !g_scratch_done[dev])
+            return fail(ctx, PMS_ERR_DEVICE, "scratch array of this device was not set up");
+        if (!g_scratch_ptr[dev]) return hip_fail(ctx, g_scratch_err[dev], "hipGetSymbolAddress(scratch)");
+        base = g_scratch_ptr[dev];
+    }
+    const int W = specs[0].W, H = specs[0].H;
+    const size_t tab_bytes = align256(tables_bytes(W, H));
+    Tables T = tables_at(base, W, H);
+    Plan P;
+    if ((st = build_plan(ctx, specs, nullptr, P, &T)) != PMS_OK) return st;
+    if (tab_bytes + P.total_bytes > PMS_NOALLOC_SCRATCH_BYTES)
+        return fail(ctx, PMS_ERR_BUDGET,
+                    "this call needs " + std::to_string(tab_bytes + P.total_bytes) +
+                        " bytes of scratch, more than PMS_NOALLOC_SCRATCH_BYTES (" +
+                        std::to_string((size_t)PMS_NOALLOC_SCRATCH_BYTES) + ")");
+    char *block = static_cast<char *>(base) + tab_bytes;
+    if ((st = build_plan(ctx, specs, block, P, &T)) != PMS_OK) return st;
+    const size_t upload = tab_bytes + P.args_bytes;
+    if (ctx->noalloc_host.size() < upload) ctx->noalloc_host.resize(upload);
+    char *host = ctx->noalloc_host.data();
+    std::memset(host, 0, tab_bytes);
+    fill_tables_host(W, H, host);
+    pack_args(P, host + tab_bytes);
+    hipError_t e = hipMemcpyAsync(base, host, upload, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "argument upload");
+    return enqueue_plan(ctx, P, block, s, false);
 }
 
 bool check_outputs(pms_context *ctx, int W, pms_plane depth, const pms_plane normal[3],
@@ -1160,6 +1261,7 @@ pms_status pms_context_create(int32_t device, size_t scratch_budget_bytes, pms_c
     if (!ctx) return PMS_ERR_OUT_OF_MEMORY;
     ctx->device = device;
     ctx->budget = scratch_budget_bytes;
+    scratch_setup(device);
     *out = ctx;
     return PMS_OK;
 }
@@ -1228,6 +1330,23 @@ pms_status pms_densify(pms_context *ctx, const pms_image *ref, const pms_pose *r
         return st;
     if (!check_batch_aliasing(ctx, specs, &st)) return st;
     return run_specs(ctx, specs, static_cast<hipStream_t>(stream));
+}
+
+pms_status pms_densify_noalloc(pms_context *ctx, const pms_image *ref, const pms_pose *ref_pose,
+                               const pms_image *nbrs, const pms_pose *nbr_poses, int32_t n_nbrs,
+                               const pms_plane *maps, const pms_pose *map_poses, int32_t n_maps,
+                               const pms_params *params, pms_plane depth_out,
+                               const pms_plane normal_out[3], pms_plane cost_out, void *stream)
+{
+    if (!ctx) return PMS_ERR_INVALID_ARG;
+    ctx->last_error.clear();
+    pms_status st = PMS_OK;
+    std::vector<JobSpec> specs(1);
+    if (!densify_spec(ctx, ref, ref_pose, nbrs, nbr_poses, n_nbrs, maps, map_poses, n_maps, params,
+                      depth_out, normal_out, cost_out, specs[0], &st))
+        return st;
+    if (!check_batch_aliasing(ctx, specs, &st)) return st;
+    return run_noalloc(ctx, specs, static_cast<hipStream_t>(stream));
 }
 
 pms_status pms_densify_batch(pms_context *ctx, const pms_job *jobs, int32_t n_jobs, void *stream)

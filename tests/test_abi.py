@@ -75,11 +75,14 @@ class _Call:
         self.map_poses = None
         self.n_maps = 0
 
-    def densify(self, ctx):
-        return self.B.lib().pms_densify(ctx, C.byref(self.ref), C.byref(self.pose), self.nbrs,
-                                        self.nposes, self.n, self.maps, self.map_poses,
-                                        self.n_maps, C.byref(self.params), self.depth,
-                                        self.normal, self.cost, None)
+    def densify(self, ctx, fn="pms_densify"):
+        return getattr(self.B.lib(), fn)(ctx, C.byref(self.ref), C.byref(self.pose), self.nbrs,
+                                         self.nposes, self.n, self.maps, self.map_poses,
+                                         self.n_maps, C.byref(self.params), self.depth,
+                                         self.normal, self.cost, None)
+
+
+DENSIFY_FNS = ["pms_densify", "pms_densify_noalloc"]
 
 
 @pytest.fixture()
@@ -90,9 +93,10 @@ def vctx(B):
     B.lib().pms_context_destroy(h)
 
 
-def test_well_formed_call_reaches_the_device_step(B, vctx):
+@pytest.mark.parametrize("fn", DENSIFY_FNS)
+def test_well_formed_call_reaches_the_device_step(B, vctx, fn):
     for dtype in (0, 1, 2):
-        assert _Call(B, dtype=dtype).densify(vctx) == DEVICE
+        assert _Call(B, dtype=dtype).densify(vctx, fn) == DEVICE
     assert b"validation-only" in B.lib().pms_last_error(vctx)
 
 
@@ -126,10 +130,11 @@ def test_well_formed_call_reaches_the_device_step(B, vctx):
     (lambda c: setattr(c, "n_maps", 2), INVALID),                     # maps missing
     (lambda c: setattr(c, "n_maps", 9), INVALID),
 ])
-def test_malformed_calls_are_rejected_before_launch(B, vctx, mutate, expect):
+@pytest.mark.parametrize("fn", DENSIFY_FNS)
+def test_malformed_calls_are_rejected_before_launch(B, vctx, mutate, expect, fn):
     c = _Call(B)
     mutate(c)
-    assert c.densify(vctx) == expect
+    assert c.densify(vctx, fn) == expect
     assert B.lib().pms_last_error(vctx) != b""
 
 
