@@ -86,3 +86,26 @@ def world_points(w, k, n, seed):
 def centre(pose):
     R, t = pose
     return -np.asarray(R, dtype=np.float64).T @ np.asarray(t, dtype=np.float64)
+
+
+GOLDEN_HALL_1920 = "hall_1920_seed0.npz"
+
+
+def load_golden_hall_1920():
+    """The FP64 oracle's stored run of the 1920x960 hall keyframe (written by
+    tests/golden/make_hall_1920.py): (depth before consistency (H, W) float64,
+    0 = invalid; cost (H, W) float64; kept-by-consistency mask (H, W) bool;
+    meta dict)."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", GOLDEN_HALL_1920)
+    g = np.load(path, allow_pickle=False)
+    meta = json.loads(str(g["meta"]))
+    code = g["depth_code"].astype(np.float64)
+    dc = meta["depth_code"]
+    lo, hi = np.log(dc["d_min"]), np.log(dc["d_max"])
+    depth = np.where(code > 0, np.exp(lo + (code - 1.0) / dc["code_max"] * (hi - lo)), 0.0)
+    cost = g["cost_code"].astype(np.float64) / 65535.0 * 2.0
+    H, W = meta["H"], meta["W"]
+    keep = np.unpackbits(g["keep_bits"])[:H * W].reshape(H, W).astype(bool)
+    return depth, cost, keep, meta
