@@ -160,6 +160,30 @@ def _traffic_records() -> list:
                 for line in f if line.startswith("<!-- traffic ")]
 
 
+# Host cores the oracle may use: those this process may run on, at most the
+# 16 that the GPU machine allots to one GPU's jobs.
+HOST_THREADS_MAX = 16
+
+
+def host_threads() -> int:
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(n, HOST_THREADS_MAX))
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def valid_pixels(W: int, H: int, params: dict) -> int:
     r = (params["patch_size"] - 1) // 2
     return W * max(0, H - 2 * r)
@@ -209,6 +233,8 @@ def cpu_baseline(w, params, budget_s: float, threads: int) -> dict:
     per_update = elapsed / updates
     kf_seconds = per_update * valid_pixels(W, H, params) * (params["iterations"] + 1.0 / 14.0)
     return {"value": 1.0 / kf_seconds, "unit": "keyframes/s", "cores": threads, "kind": "oracle",
+            "nproc": os.cpu_count(), "cpu_model": cpu_model(),
+            "affinity_cores": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None,
             "sample": (f"red half-sweeps over rows {rows[0]}-{rows[-1] + band - 1} of the "
                        f"{W}x{H} reference ({updates} pixel updates, {elapsed:.1f} s wall on "
                        f"{threads} threads), scaled by {valid_pixels(W, H, params)} valid pixels "
@@ -533,21 +559,33 @@ def batch_section(args, torch, pms, synth, pool, ctx) -> dict:
                                 "speedup": t_small_plain / t_small_batch}}
 
 
-def serving_section(args, torch, pms, synth, pool, ctx, warm: bool, horizon: float) -> dict:
-    """Keyframe streams through the continuous-batching server. A keyframe
-    whose stream predecessor is already done starts from the predecessor's
-    planes carried over by plane-map warping (Sec. III-B) and runs
-    --serve-warm-iters iterations; otherwise it starts from random planes
-    with the full iterations. Accuracy against the rendered ground truth is
-    measured on every 8th served keyframe (fewer past 360 requests, about
-    45 in all) and on the same keyframes
-    densified by the plain FP32 path with the full iterations."""
+def serving_section(args, torch, pms, synth, pool, ctx, warm: bool, horizon: float,
+                    rate: float | None = None, light: bool = False) -> dict:
+    """Keyframe streams through the continuous-batching server.
+
+    warm: each stream is one camera with one resolution (drawn per stream),
+    walking its window; a keyframe whose stream predecessor is already done
+    starts from the predecessor's planes carried over by plane-map warping
+    (Sec. III-B) and runs --serve-warm-iters iterations, and each is filtered
+    against its stream's four previous depth maps.
+    not warm (the serving configuration as specified): every keyframe draws
+    its resolution and reference uniformly and starts from random planes
+    with the full iterations.
+    Accuracy against the rendered ground truth is measured on every 8th
+    served keyframe (fewer past 360 requests, about 45 in all) and on the same
+    keyframes densified by the plain FP32 path with the full iterations;
+    `light` skips that and the solo re-runs (rate sweep points)."""
+    rate = args.serve_rate if rate is None else rate
     from paper_2211_16266_amd import serving
     dev = torch.device("cuda:0")
     imgs32 = {W: [torch.from_numpy(a).to(dev) for a in w.images] for W, w in pool.items()}
     imgs16 = {W: [t.half() for t in ts] for W, ts in imgs32.items()}
-    reqs = synth.stream_requests(args.serve_streams, args.serve_rate, horizon,
-                                 seed=args.seed + 7)
+    if warm:
+        reqs = synth.stream_requests(args.serve_streams, rate, horizon, seed=args.seed + 7)
+    else:
+        # (time, stream, position in the arrival order, job): a resolution per keyframe
+        reqs = [(t, st, i, mj) for i, (t, st, mj) in
+                enumerate(synth.poisson_requests(args.serve_streams, rate, horizon, seed=args.seed + 7))]
     warp_ctx = pms.Context(0)
     server = pms.Server(int(args.serve_arena_gib * 2**30), max_jobs=args.serve_max_jobs,
                         ctx=pms.Context(0))
@@ -604,10 +642,11 @@ def serving_section(args, torch, pms, synth, pool, ctx, warm: bool, horizon: flo
     def on_done(rq, res):
         i, s, k, mj = rq.tag
         d, n, _ = rq.job.out
-        if s not in latest or latest[s][0] < k:
-            latest[s] = (k, mj.W, mj.ref, d, n)
-        consistency_window(s, k, mj, rq.job)
-        if i % sample_every == 0:
+        if warm:
+            if s not in latest or latest[s][0] < k:
+                latest[s] = (k, mj.W, mj.ref, d, n)
+            consistency_window(s, k, mj, rq.job)
+        if i % sample_every == 0 and not light:
             samples.append((mj, rq.job.warm, rq.job))
 
     def ready(rq):
@@ -616,14 +655,14 @@ def serving_section(args, torch, pms, synth, pool, ctx, warm: bool, horizon: flo
         return k == 0 or (s in latest and latest[s][0] >= k - 1)
 
     log(f"serving {len(requests)} keyframes from {args.serve_streams} streams at "
-        f"{args.serve_rate}/s each over {horizon:.0f} s "
-        f"({'warm starts from the stream predecessor' if warm else 'random initialisation'})")
+        f"{rate}/s each over {horizon:.0f} s "
+        f"({'warm starts from the stream predecessor' if warm else 'random initialisation, a resolution per keyframe'})")
     out = serving.run(server, requests, on_done=on_done, log=log, keep_jobs=False,
                       ready=ready if warm else None)
     torch.cuda.synchronize()
     # the same keyframes alone through the same path: bitwise equal
     solo_equal = True
-    for mj, warm, jd in samples[:3]:
+    for mj, _, jd in samples[:3]:
         solo = pms.densify_job(pms.job(jd.ref, jd.nbrs, jd.ref_pose, jd.nbr_poses, jd.params,
                                        init=jd.init), ctx=server.ctx)
         torch.cuda.synchronize()
@@ -637,28 +676,30 @@ def serving_section(args, torch, pms, synth, pool, ctx, warm: bool, horizon: flo
         return _gt_accuracy(depth.cpu().numpy(), w.gt_depth[mj.ref], r)[1]
 
     served_acc = [gt_acc(jd.out[0], mj) for mj, _, jd in samples]
-    plain_jobs = []
+    plain_jobs, plain_acc, t_plain = [], [], float("nan")
     for mj, _, _ in samples:
         w = pool[mj.W]
         plain_jobs.append(pms.job(imgs32[mj.W][mj.ref], [imgs32[mj.W][j] for j in mj.nbrs],
                                   w.poses[mj.ref], [w.poses[j] for j in mj.nbrs],
                                   dict(w.params, seed=mj.seed)))
-    for jd in plain_jobs[:2]:
-        pms.densify(jd.ref, jd.nbrs, jd.ref_pose, jd.nbr_poses, jd.params, out=jd.out, ctx=ctx)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for jd in plain_jobs:
-        pms.densify(jd.ref, jd.nbrs, jd.ref_pose, jd.nbr_poses, jd.params, out=jd.out, ctx=ctx)
-    torch.cuda.synchronize()
-    t_plain = time.perf_counter() - t0
-    plain_acc = [gt_acc(jd.out[0], mj) for (mj, _, _), jd in zip(samples, plain_jobs)]
+    if plain_jobs:
+        for jd in plain_jobs[:2]:
+            pms.densify(jd.ref, jd.nbrs, jd.ref_pose, jd.nbr_poses, jd.params, out=jd.out, ctx=ctx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for jd in plain_jobs:
+            pms.densify(jd.ref, jd.nbrs, jd.ref_pose, jd.nbr_poses, jd.params, out=jd.out, ctx=ctx)
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t0
+        plain_acc = [gt_acc(jd.out[0], mj) for (mj, _, _), jd in zip(samples, plain_jobs)]
     warp_ctx.close()
     kept = float(sum(int(t.item()) for t in filt["kept"]))
     valid = float(sum(int(t.item()) for t in filt["valid"]))
     geo_ctx.close()
-    offered = args.serve_streams * args.serve_rate
-    return {"workload": f"{args.serve_streams} keyframe streams x Poisson({args.serve_rate}/s), "
-                        "one width per stream from 960/1920/2880, N~U{3..6}, f16 images",
+    offered = args.serve_streams * rate
+    widths = "one width per stream" if warm else "a width per keyframe"
+    summary = {"workload": f"{args.serve_streams} keyframe streams x Poisson({rate}/s), "
+                           f"{widths} from 960/1920/2880, N~U{{3..6}}, f16 images",
             "warm_start": warm, "warm_iterations": args.serve_warm_iters if warm else None,
             "warm_started": count["warm"], "cold_started": count["cold"],
             "horizon_s": horizon, "requests": out["requests"],
@@ -670,13 +711,20 @@ def serving_section(args, torch, pms, synth, pool, ctx, warm: bool, horizon: flo
             "latency_ms_arrivals_after_2s": _late_latency(out["results"], 2.0),
             "mean_batch_occupancy": out["mean_occupancy"], "ticks": out["ticks"],
             "max_jobs": args.serve_max_jobs, "arena_peak_gib": out["arena_peak_bytes"] / 2**30,
-            "within_1pct_of_gt": {"served": float(np.mean(served_acc)),
-                                  "plain_fp32_full_iterations": float(np.mean(plain_acc)),
+            "within_1pct_of_gt": {"served": float(np.mean(served_acc)) if samples else None,
+                                  "plain_fp32_full_iterations": float(np.mean(plain_acc)) if samples else None,
                                   "keyframes": len(samples)},
-            "plain_fp32_keyframes_per_s_on_those": len(plain_jobs) / t_plain,
+            "plain_fp32_keyframes_per_s_on_those": len(plain_jobs) / t_plain if plain_jobs else None,
             "consistency_window": {"keyframes_filtered": filt["filtered"],
                                    "kept_fraction_of_valid": kept / valid if valid else None},
             "solo_rerun_bitwise_equal": bool(solo_equal), "solo_rerun_checked": min(3, len(samples))}
+    if light:
+        for k in ("within_1pct_of_gt", "plain_fp32_keyframes_per_s_on_those", "consistency_window",
+                  "solo_rerun_bitwise_equal", "solo_rerun_checked"):
+            summary.pop(k, None)
+    if not warm:
+        summary.pop("consistency_window", None)
+    return summary
 
 
 def _late_latency(results, after_s: float) -> dict:
@@ -788,7 +836,11 @@ def main() -> int:
     ap.add_argument("--schedule", default=None, metavar="WAVE_ROWS,WAVES_X",
                     help="use this tile shape instead of autotuning (e.g. 4,2)")
     ap.add_argument("--batch-reps", type=int, default=3)
-    ap.add_argument("--serve-horizon", type=float, default=15.0,
+    ap.add_argument("--serve-sweep", default="6,12,18",
+                    help="offered keyframes/s (all streams) of the random-initialisation rate sweep; "
+                         "empty to skip")
+    ap.add_argument("--serve-sweep-horizon", type=float, default=10.0)
+    ap.add_argument("--serve-horizon", type=float, default=60.0,
                     help="seconds of request arrivals in the serving section (0 = skip)")
     ap.add_argument("--serve-random-horizon", type=float, default=15.0,
                     help="seconds of arrivals of the random-initialisation serving run (0 skips it)")
@@ -899,6 +951,13 @@ def main() -> int:
     lat = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(K)])
     kern = {name: ctx.profile_read(name)
             for name in ("halfsweep", "init", "refstats", "finalize", "consistency")}
+    # the work the half-sweeps actually execute, counted in one more step by
+    # the counting variant of the same kernel (same results, not timed)
+    log("counting the half-sweeps' executed work (one untimed step)")
+    ctx.work_count_enable(True)
+    step()
+    counts = ctx.work_count_read()
+    ctx.work_count_enable(False)
 
     wall = t1 - t0
     kfps = K / wall
@@ -908,9 +967,16 @@ def main() -> int:
     evals_per_kf = vpx * N * (1 + hyps * params["iterations"])
     n_half, ms_half = kern["halfsweep"]
     avg_half_s = ms_half / max(n_half, 1) / 1e3
-    evals_per_launch = (vpx // 2) * hyps * N
+    launches_per_step = 2 * params["iterations"]
+    # nominal units: every candidate of every updated pixel scored on every view
+    nominal_per_launch = (vpx // 2) * hyps * N
+    # executed units: the (pixel, candidate, view) evaluations the kernel ran
+    evals_per_launch = counts["view_evals"] / launches_per_step
     slots_per_launch = evals_per_launch * (P * SLOTS_PER_SAMPLE + SLOTS_PER_EVAL)
     achieved = slots_per_launch / avg_half_s / 1e12
+    nominal_slots = nominal_per_launch * (P * SLOTS_PER_SAMPLE + SLOTS_PER_EVAL)
+    cand = counts["prop_candidates"] + counts["refine_trials"]
+    nominal_views = counts["pixels"] * hyps * N
     img_bytes = (N + 1) * W * H * w.images[0].itemsize
     hbm_bytes = (vpx // 2) * HBM_BYTES_PER_UPDATE + img_bytes
     traffic = measured_traffic(schedule)
@@ -953,12 +1019,27 @@ def main() -> int:
             "traffic_detail": traffic,
             "avg_launch_ms": avg_half_s * 1e3,
             "launches": n_half,
-            "algorithmic_per_launch": {"ncc_evals": evals_per_launch, "slots": slots_per_launch,
-                                       "hbm_bytes": hbm_bytes},
+            "algorithmic_per_launch": {"ncc_evals": evals_per_launch, "samples": evals_per_launch * P,
+                                       "slots": slots_per_launch, "hbm_bytes": hbm_bytes,
+                                       "unit": "executed (pixel, candidate, view) NCC evaluations"},
             "pricing": {"slots_per_sample": SLOTS_PER_SAMPLE, "slots_per_eval": SLOTS_PER_EVAL,
                         "isa_slots_per_sample": ISA_SLOTS_PER_SAMPLE, "isa_slots_per_eval": ISA_SLOTS_PER_EVAL},
+            # every candidate of every pixel counted as scored on every view
+            "contract_frac": nominal_slots / avg_half_s / 1e12 / PEAK_TSLOTS,
+            "executed": {
+                "ncc_evals_per_launch": evals_per_launch,
+                "nominal_ncc_evals_per_launch": nominal_per_launch,
+                "executed_of_nominal": counts["view_evals"] / nominal_views,
+                "views_pruned_of_nominal": counts["views_pruned"] / nominal_views,
+                "candidates_skipped_repeat": counts["skipped_repeat"] / cand,
+                "candidates_skipped_geometry": counts["skipped_geometry"] / cand,
+                "candidates_facing_rejected": counts["facing_rejects"] / cand,
+                "counts_per_step": counts,
+            },
             "isa_priced_frac": evals_per_launch * (P * ISA_SLOTS_PER_SAMPLE + ISA_SLOTS_PER_EVAL)
                                / avg_half_s / 1e12 / PEAK_TSLOTS,
+            "isa_priced_contract_frac": nominal_per_launch * (P * ISA_SLOTS_PER_SAMPLE + ISA_SLOTS_PER_EVAL)
+                                        / avg_half_s / 1e12 / PEAK_TSLOTS,
             "hbm_achieved_GBs": hbm_bytes / avg_half_s / 1e9,
             "hbm_frac": hbm_bytes / avg_half_s / 1e9 / HBM_PEAK_GBS,
         },
@@ -983,9 +1064,23 @@ def main() -> int:
         if not args.serve_cold and args.serve_random_horizon > 0:
             result["serving_random_init"] = serving_section(args, torch, pms, synth, pool, ctx,
                                                             warm=False, horizon=args.serve_random_horizon)
+        if args.serve_sweep:
+            # the random-initialisation form at lower offered rates: where the
+            # achieved rate keeps up with the offered one and latency stays flat
+            sweep = []
+            for total in (float(v) for v in args.serve_sweep.split(",")):
+                r = serving_section(args, torch, pms, synth, pool, ctx, warm=False,
+                                    horizon=args.serve_sweep_horizon, rate=total / args.serve_streams,
+                                    light=True)
+                sweep.append({k: r[k] for k in ("offered_keyframes_per_s", "keyframes_per_s", "requests",
+                                                "horizon_s", "wall_s", "latency_ms",
+                                                "latency_ms_arrivals_after_2s", "mean_batch_occupancy")})
+            result["serving_rate_sweep"] = {"init": "random, full iterations, a width per keyframe",
+                                            "points": sweep}
     if args.cpu_budget > 0:
-        threads = min(os.cpu_count() or 1, 16)
-        log(f"cpu baseline: oracle on {threads} threads, ~{args.cpu_budget:.0f} s")
+        threads = host_threads()
+        log(f"cpu baseline: oracle on {threads} threads ({cpu_model()}, nproc {os.cpu_count()}), "
+            f"~{args.cpu_budget:.0f} s")
         result["cpu_baseline"] = cpu_baseline(w, params, args.cpu_budget, threads)
     else:
         result["cpu_baseline"] = None

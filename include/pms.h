@@ -398,6 +398,37 @@ pms_status pms_philox_stream(pms_context *ctx, uint64_t key0, uint64_t key1, uin
    "fuse", "coverage", "view_filter") since the last read, and clears them.
    A graph launch is timed as one "batch". */
 pms_status pms_profile_enable(pms_context *ctx, int32_t on);
+
+/* Executed-work counters of the half-sweeps (Sec. III-C: propagation and
+   refinement), for measuring throughput against the work actually done.
+   While enabled, every half-sweep launch of the context runs a variant that
+   counts, per pixel update, the candidates it considers, skips and scores
+   and the (pixel, candidate, view) NCC evaluations it executes, and adds
+   them to device counters (one atomic per counter and workgroup). Results
+   are bit for bit those of the uncounted kernels. pms_work_count_enable
+   allocates the counters on first use (zeroed); pms_work_count_read
+   synchronises the device, copies the totals since the last reset into
+   *out (all zero if never enabled) and zeroes them when reset != 0.
+   Invariants: prop_candidates + refine_trials = skipped_geometry +
+   skipped_repeat + scored; view_evals + views_pruned = n_views x (scored -
+   facing_rejects) for a job with n_views neighbours. */
+#define PMS_WORK_FIELDS 9
+typedef struct {
+    int64_t pixels;           /* pixel updates                                */
+    int64_t prop_candidates;  /* propagation offsets considered             */
+    int64_t refine_trials;    /* refinement trials considered                */
+    int64_t skipped_geometry; /* dropped unscored: neighbour outside the band
+                                 or invalid, plane behind the ray or depth out
+                                 of range, refined normal not facing          */
+    int64_t skipped_repeat;   /* propagation candidates equal to the current
+                                 plane or the previous candidate             */
+    int64_t scored;           /* candidates whose cost was evaluated          */
+    int64_t facing_rejects;   /* scored planes not facing every sample ray   */
+    int64_t view_evals;       /* NCC evaluations executed (P samples each)   */
+    int64_t views_pruned;     /* views skipped by the top-k bound            */
+} pms_work_counts;
+pms_status pms_work_count_enable(pms_context *ctx, int32_t on);
+pms_status pms_work_count_read(pms_context *ctx, pms_work_counts *out, int32_t reset);
 pms_status pms_profile_read(pms_context *ctx, const char *name, int64_t *launches,
                             double *total_ms);
 

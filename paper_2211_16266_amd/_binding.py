@@ -70,6 +70,14 @@ class Job(C.Structure):
                 ("cost_out", Plane), ("init_depth", Plane), ("init_normal", Plane * 3)]
 
 
+WORK_FIELDS = ("pixels", "prop_candidates", "refine_trials", "skipped_geometry", "skipped_repeat",
+               "scored", "facing_rejects", "view_evals", "views_pruned")
+
+
+class WorkCounts(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in WORK_FIELDS]
+
+
 class Schedule(C.Structure):
     _fields_ = [("wave_rows", C.c_int32), ("waves_x", C.c_int32), ("lanes_per_pixel", C.c_int32)]
 
@@ -112,6 +120,8 @@ def lib() -> C.CDLL:
         L.pms_philox_stream.argtypes = [C.c_void_p, C.c_uint64, C.c_uint64, C.c_uint64, C.c_int64,
                                         C.c_void_p, C.c_void_p]
         L.pms_profile_enable.argtypes = [C.c_void_p, C.c_int32]
+        L.pms_work_count_enable.argtypes = [C.c_void_p, C.c_int32]
+        L.pms_work_count_read.argtypes = [C.c_void_p, P(WorkCounts), C.c_int32]
         L.pms_profile_read.argtypes = [C.c_void_p, C.c_char_p, P(C.c_int64), P(C.c_double)]
         L.pms_densify_batch.argtypes = [C.c_void_p, P(Job), C.c_int32, C.c_void_p]
         L.pms_batch_create.argtypes = [C.c_void_p, P(Job), C.c_int32, P(C.c_void_p)]
@@ -136,6 +146,7 @@ def lib() -> C.CDLL:
         for name in ("pms_default_params", "pms_context_create", "pms_context_destroy",
                      "pms_densify", "pms_densify_noalloc", "pms_eval_cost", "pms_halfsweep", "pms_consistency",
                      "pms_philox_stream", "pms_profile_enable", "pms_profile_read",
+                     "pms_work_count_enable", "pms_work_count_read",
                      "pms_densify_batch", "pms_batch_create", "pms_batch_run", "pms_batch_bytes",
                      "pms_batch_destroy", "pms_get_schedule", "pms_set_schedule", "pms_autotune",
                      "pms_server_create", "pms_server_submit", "pms_server_step",
@@ -261,6 +272,16 @@ class Context:
 
     def profile_enable(self, on: bool = True) -> None:
         self.check(lib().pms_profile_enable(self.handle, int(bool(on))), "pms_profile_enable")
+
+    def work_count_enable(self, on: bool = True) -> None:
+        """Half-sweeps of this context count their executed work while on."""
+        self.check(lib().pms_work_count_enable(self.handle, int(on)), "pms_work_count_enable")
+
+    def work_count_read(self, reset: bool = True) -> dict:
+        """Totals of the half-sweep work counters (synchronises the device)."""
+        w = WorkCounts()
+        self.check(lib().pms_work_count_read(self.handle, C.byref(w), int(reset)), "pms_work_count_read")
+        return {n: int(getattr(w, n)) for n in WORK_FIELDS}
 
     def get_schedule(self) -> dict:
         sc = Schedule()

@@ -84,6 +84,9 @@ struct pms_context {
     bool capturing = false;
     std::string last_error;
     bool profiling = false;
+    // executed-work counters of the half-sweeps (pms_work_count_*)
+    bool work_counts_on = false;
+    unsigned long long *work_counts = nullptr;
     std::vector<char> noalloc_host;  // pageable upload buffer of pms_densify_noalloc
     std::vector<TimedLaunch> launches;
     std::vector<hipEvent_t> event_pool;
@@ -290,10 +293,11 @@ pms::ViewPoseF relative_pose(const pms_pose &ref, const pms_pose &nbr)
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// A re-laid-out image holds, for every bilinear cell, the corner value and
-// its three differences in FP32 whatever the input type: (H + 1) rows of
-// 2W + 4 cells of 16 bytes.
-size_t pad_elem_size(int) { return sizeof(float4); }
+// A re-laid-out image holds (H + 1) rows of 2W + 4 bilinear cells: 16 bytes
+// (corner value and its three differences in FP32) for FP32 images, 8 bytes
+// for FP16 (the four corners as halves) and 8-bit ones (corner and three
+// differences of the raw values, as halves).
+size_t pad_elem_size(int dtype) { return dtype == PMS_F32 ? sizeof(float4) : dtype == PMS_F16 ? sizeof(pms::Cell8) : sizeof(pms::Cell8d); }
 long long pad_cells(int W, int H) { return (long long)(H + 1) * (2 * (long long)W + 4); }
 
 pms_status set_device(pms_context *ctx)
@@ -548,6 +552,7 @@ void fill_sweep_args(pms::SweepArgs &A, const JobSpec &J, const Geometry &g, con
     A.top_k = p->top_k > 0 ? p->top_k : (J.n_nbrs + 1) / 2;
     A.inv_k = (float)(1.0 / A.top_k);
     A.var_floor = (float)p->ncc_var_floor;
+    A.var_floor_s = (float)(J.ref->dtype == PMS_U8 ? p->ncc_var_floor * 255.0 * 255.0 : p->ncc_var_floor);
     A.dmin = (float)p->depth_min;
     A.dmax = (float)p->depth_max;
     A.inv_dmin = (float)(1.0 / p->depth_min);
@@ -892,11 +897,27 @@ pms_status upload_args(pms_context *ctx, const Plan &P, void *dev, hipStream_t s
     return PMS_OK;
 }
 
+// The half-sweep variant that also counts its executed work.
+template <int DT>
+void launch_counted_dt(const Variant &v, const pms::Launch &L, dim3 grid, hipStream_t s)
+{
+    using namespace pms;
+    if (v.lpp == 2) hipLaunchKernelGGL((k_halfsweep_counted<DT, 2, 18, true>), grid, dim3(BLOCK), 0, s, L);
+    else if (v.lpp == 8) hipLaunchKernelGGL((k_halfsweep_counted<DT, 8, 8, true>), grid, dim3(BLOCK), 0, s, L);
+    else if (v.full && v.spl == 9) hipLaunchKernelGGL((k_halfsweep_counted<DT, 4, 9, true>), grid, dim3(BLOCK), 0, s, L);
+    else if (v.full && v.spl == 16) hipLaunchKernelGGL((k_halfsweep_counted<DT, 4, 16, true>), grid, dim3(BLOCK), 0, s, L);
+    else if (v.spl == 4) hipLaunchKernelGGL((k_halfsweep_counted<DT, 4, 4, false>), grid, dim3(BLOCK), 0, s, L);
+    else if (v.spl == 9) hipLaunchKernelGGL((k_halfsweep_counted<DT, 4, 9, false>), grid, dim3(BLOCK), 0, s, L);
+    else if (v.spl == 13) hipLaunchKernelGGL((k_halfsweep_counted<DT, 4, 13, false>), grid, dim3(BLOCK), 0, s, L);
+    else hipLaunchKernelGGL((k_halfsweep_counted<DT, 4, 16, false>), grid, dim3(BLOCK), 0, s, L);
+}
+
 template <int KIND, int DT>
 void launch_tiles_dt(const Variant &v, const pms::Launch &L, dim3 grid, hipStream_t s)
 {
     using namespace pms;
-    if (v.lpp == 2) hipLaunchKernelGGL((k_tiles<KIND, DT, 2, 18, true>), grid, dim3(BLOCK), 0, s, L);
+    if (KIND == TK_HALFSWEEP && L.counts) launch_counted_dt<DT>(v, L, grid, s);
+    else if (v.lpp == 2) hipLaunchKernelGGL((k_tiles<KIND, DT, 2, 18, true>), grid, dim3(BLOCK), 0, s, L);
     else if (v.lpp == 8) hipLaunchKernelGGL((k_tiles<KIND, DT, 8, 8, true>), grid, dim3(BLOCK), 0, s, L);
     else if (v.full && v.spl == 9) hipLaunchKernelGGL((k_tiles<KIND, DT, 4, 9, true>), grid, dim3(BLOCK), 0, s, L);
     else if (v.full && v.spl == 16) hipLaunchKernelGGL((k_tiles<KIND, DT, 4, 16, true>), grid, dim3(BLOCK), 0, s, L);
@@ -931,6 +952,7 @@ pms_status enqueue_plan(pms_context *ctx, const Plan &P, char *dev, hipStream_t 
             L.entries = reinterpret_cast<const pms::Entry *>(dev + P.off_entries) + R.entry_off;
             L.n_entries = R.n_entries;
             L.slots = R.total;
+            L.counts = R.kind == KK_HALFSWEEP && ctx->work_counts_on ? ctx->work_counts : nullptr;
             dim3 grid(8u * (unsigned)L.slots);
             switch (R.kind) {
             case KK_IO: hipLaunchKernelGGL(pms::k_pad, grid, dim3(pms::BLOCK), 0, s, L); break;
@@ -1274,6 +1296,7 @@ pms_status pms_context_destroy(pms_context *ctx)
         (void)hipDeviceSynchronize();
     }
     if (ctx->work) (void)hipFree(ctx->work);
+    if (ctx->work_counts) (void)hipFree(ctx->work_counts);
     for (auto &kv : ctx->tables) (void)hipFree(kv.second.row);
     for (auto &sl : ctx->staging) {
         if (sl.host) (void)hipHostFree(sl.host);
@@ -1868,6 +1891,50 @@ pms_status pms_profile_enable(pms_context *ctx, int32_t on)
 {
     if (!ctx) return PMS_ERR_INVALID_ARG;
     ctx->profiling = on != 0;
+    return PMS_OK;
+}
+
+pms_status pms_work_count_enable(pms_context *ctx, int32_t on)
+{
+    if (!ctx) return PMS_ERR_INVALID_ARG;
+    ctx->last_error.clear();
+    if (on && !ctx->work_counts) {
+        pms_status st = set_device(ctx);
+        if (st != PMS_OK) return st;
+        void *p = nullptr;
+        if (hipMalloc(&p, PMS_WORK_FIELDS * sizeof(unsigned long long)) != hipSuccess)
+            return fail(ctx, PMS_ERR_OUT_OF_MEMORY, "hipMalloc of the work counters failed");
+        hipError_t e = hipMemset(p, 0, PMS_WORK_FIELDS * sizeof(unsigned long long));
+        if (e != hipSuccess) {
+            (void)hipFree(p);
+            return hip_fail(ctx, e, "hipMemset of the work counters");
+        }
+        ctx->work_counts = static_cast<unsigned long long *>(p);
+    }
+    ctx->work_counts_on = on != 0;
+    return PMS_OK;
+}
+
+pms_status pms_work_count_read(pms_context *ctx, pms_work_counts *out, int32_t reset)
+{
+    if (!ctx || !out) return PMS_ERR_INVALID_ARG;
+    ctx->last_error.clear();
+    std::memset(out, 0, sizeof *out);
+    if (!ctx->work_counts) return PMS_OK;
+    pms_status st = set_device(ctx);
+    if (st != PMS_OK) return st;
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipDeviceSynchronize");
+    unsigned long long v[PMS_WORK_FIELDS];
+    e = hipMemcpy(v, ctx->work_counts, sizeof v, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(ctx, e, "work counter read");
+    static_assert(PMS_WORK_FIELDS == pms::WC_FIELDS, "counter fields");
+    int64_t *dst = &out->pixels;
+    for (int f = 0; f < PMS_WORK_FIELDS; ++f) dst[f] = (int64_t)v[f];
+    if (reset) {
+        e = hipMemset(ctx->work_counts, 0, sizeof v);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipMemset of the work counters");
+    }
     return PMS_OK;
 }
 

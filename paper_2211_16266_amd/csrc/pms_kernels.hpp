@@ -61,17 +61,19 @@ constexpr int MAXOFF = 16;    // propagation offsets
 constexpr int MAXTRIAL = 16;  // refinement trials
 constexpr int BLOCK = 256;    // threads per workgroup (4 waves)
 
-// Occupancy target of the PatchMatch kernels (waves per SIMD): 4 for up to
-// 9 samples per lane, where the compiler would otherwise settle for 3 waves
-// to avoid a couple of spill slots outside the sample loop (3 for the
-// per-view cost evaluation, which keeps more state and cannot reach 4);
-// the larger variants keep the compiler's choice (2 waves, which hold the
-// short and the general sample forms without spills: forcing 3 spills
-// inside the sample loop and runs slower).
+// Occupancy target of the PatchMatch kernels (waves per SIMD). Up to 9
+// samples per lane: exactly 3 (168 VGPRs; measured at 1920x960, 4
+// neighbours: 51.3 ms per keyframe, against 54.2 ms at exactly 4 waves,
+// 59.8 ms at 2, and 58 ms when the compiler may choose between 3 and 8),
+// at least 3 for the per-view cost evaluation. 13 and 16 samples per lane: exactly 2, with
+// up to 256 VGPRs, so that the compiler issues a view's gathers together
+// before it waits for them (with room for 3 it waits after each gather: the
+// 3840x1920 8-bit courtyard then takes 1013 ms per keyframe instead of 847).
 #define PMS_OCCUPANCY(KIND, SPL) \
-    __attribute__((amdgpu_waves_per_eu((SPL) <= 9 ? ((KIND) == TK_EVAL ? 3 : 4) : 1, 8)))
-// Re-laid-out neighbour image: H + 1 rows of 2W + 4 bilinear cells (16
-// bytes); logical column x is stored at x + W/2 + 2, logical row y at y + 1.
+    __attribute__((amdgpu_waves_per_eu((SPL) <= 9 ? 3 : 2, (SPL) <= 9 ? ((KIND) == TK_EVAL ? 8 : 3) : 2)))
+// Re-laid-out neighbour image: H + 1 rows of 2W + 4 bilinear cells (16 or
+// 8 bytes, see Cell8); logical column x is stored at x + W/2 + 2, logical
+// row y at y + 1.
 
 // dtype codes of the C ABI
 constexpr int DT_F32 = 0, DT_F16 = 1, DT_U8 = 2;
@@ -98,7 +100,9 @@ struct SweepArgs {
     float inv_P;
     int n_views, top_k;
     float inv_k;  // fl(1 / top_k)
-    float var_floor;
+    float var_floor;     // of the reference patch variance
+    float var_floor_s;   // of the warped samples' variance, in their cells'
+                         // units (8-bit cells hold raw 0..255: x 255^2)
     float dmin, dmax, inv_dmin, inv_dmax;
     float kx, cx, ky, cy;  // u = lam * kx + cx, v = phi * ky + cy
     float patch_chord;     // bound on |b_q - b_p| over the patch, with a margin
@@ -142,6 +146,20 @@ struct SweepArgs {
     long long init_pitch;
 };
 
+// A bilinear cell of a re-laid-out neighbour image, for the corners a, b
+// (row r0) and e, f (row r1). FP32 images: the corner value and its three
+// differences a, b - a, e - a, (f - e) - (b - a) in FP32 (float4, 16
+// bytes). FP16 images: the four corner values as halves (a, b | e, f), 8
+// bytes, exact. 8-bit images: the corner value and its three differences
+// as halves of the raw values 0..255, 8 bytes, exact (integers within
+// +-510).
+struct Cell8 {
+    unsigned ab, ef;
+};
+struct Cell8d {
+    unsigned lo, hi;
+};
+
 template <int DT>
 struct Storage;
 template <>
@@ -152,13 +170,21 @@ struct Storage<DT_F32> {
 template <>
 struct Storage<DT_F16> {
     using ref_t = __half;
-    using pad_t = float4;
+    using pad_t = Cell8;
 };
 template <>
 struct Storage<DT_U8> {
     using ref_t = uint8_t;
-    using pad_t = float4;
+    using pad_t = Cell8d;
 };
+
+// log2 of a cell's size in bytes: sample offsets are cell index << shift
+template <typename PT>
+constexpr int cell_shift()
+{
+    static_assert(sizeof(PT) == 16 || sizeof(PT) == 8, "cells are 8 or 16 bytes");
+    return sizeof(PT) == 16 ? 4 : 3;
+}
 
 // ---------------------------------------------------------------------------
 // small helpers
@@ -216,14 +242,61 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, int b
 }
 
 // Bilinear sample from the cell at byte offset `off` of a re-laid-out
-// neighbour image (corner value and its three differences): one 16-byte
-// buffer load and three FMAs (au, av: fractions along x, y).
-__device__ __forceinline__ float bilinear(__amdgpu_buffer_rsrc_t r, int off, float au, float av)
+// neighbour image (au, av: fractions along x, y).
+template <typename PT>
+__device__ __forceinline__ float bilinear(__amdgpu_buffer_rsrc_t r, int off, float au, float av);
+
+// FP32 cell (corner value and its three differences): one 16-byte buffer
+// load and three FMAs.
+template <>
+__device__ __forceinline__ float bilinear<float4>(__amdgpu_buffer_rsrc_t r, int off, float au, float av)
 {
     const float4 q = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
     const float top = fmaf(au, q.y, q.x);
     const float dv = fmaf(au, q.w, q.z);
     return fmaf(av, dv, top);
+}
+
+// lo + t (hi - lo) for the two halves of w, as fl(t hi + fl(lo - t lo)) in
+// FP32: the compiler makes each step one v_fma_mix_f32, which reads the
+// half operand exactly.
+__device__ __forceinline__ float lerp_halves(unsigned w, float t)
+{
+    const float lo = (float)__builtin_bit_cast(_Float16, (unsigned short)(w & 0xffffu));
+    const float hi = (float)__builtin_bit_cast(_Float16, (unsigned short)(w >> 16));
+    return fmaf(t, hi, fmaf(-t, lo, lo));
+}
+
+
+// Halves of a 32-bit word as floats (exact).
+__device__ __forceinline__ float half_lo(unsigned w)
+{
+    return (float)__builtin_bit_cast(_Float16, (unsigned short)(w & 0xffffu));
+}
+__device__ __forceinline__ float half_hi(unsigned w)
+{
+    return (float)__builtin_bit_cast(_Float16, (unsigned short)(w >> 16));
+}
+
+// Cell of a corner and three differences in halves: one 8-byte buffer load
+// and three FMAs, two of them mixed (the same blend as the FP32 cell).
+template <>
+__device__ __forceinline__ float bilinear<Cell8d>(__amdgpu_buffer_rsrc_t r, int off, float au, float av)
+{
+    const uint2 q = __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    const float top = fmaf(au, half_hi(q.x), half_lo(q.x));
+    const float dv = fmaf(au, half_hi(q.y), half_lo(q.y));
+    return fmaf(av, dv, top);
+}
+
+// Cell of four corner halves: one 8-byte buffer load, six FMAs (four mixed).
+template <>
+__device__ __forceinline__ float bilinear<Cell8>(__amdgpu_buffer_rsrc_t r, int off, float au, float av)
+{
+    const uint2 q = __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    const float top = lerp_halves(q.x, au);
+    const float bot = lerp_halves(q.y, au);
+    return fmaf(av, bot, fmaf(-av, top, top));
 }
 
 __device__ __forceinline__ void bearing(const SweepArgs &A, int x, int y, float b[3])
@@ -471,7 +544,7 @@ __device__ __forceinline__ void stage_rays(const SweepArgs &A, const double bp[3
 
 // Sets up view j for plane (n, c) at the pixel of `pt`; mc = -c. Reads the
 // poses from the workgroup's stage and R_j b_p from the lane's ray stage.
-template <int LPP, int SPL>
+template <int LPP, int SPL, int SH>
 __device__ __forceinline__ void view_setup(const SweepArgs &A, const Patch<SPL> &pt, int j, double mc,
                                            double nbp, float n0, float n1, float n2, ViewSetup &o)
 {
@@ -500,7 +573,7 @@ __device__ __forceinline__ void view_setup(const SweepArgs &A, const Patch<SPL> 
         // anchor position in the re-laid-out storage ((H + 1) rows of Wp
         // cells, the image starting at row 1, column W/2 + 2)
         const int U0p = U0 + (A.W >> 1) + 2, V0p = V0 + 1;
-        o.base = (V0p * A.Wp + U0p) * (int)sizeof(float4);
+        o.base = (V0p * A.Wp + U0p) << SH;
     }
     // centre turned about the vertical by -lam0 (FP64). Its longitude is
     // within a pixel and a half of lam0 (half a pixel, plus the anchor
@@ -591,7 +664,7 @@ __device__ __forceinline__ void get_setup(const SetupLds &L, int slot, ViewSetup
 // their (masked) sum. LON / LAT select the short atan form for the
 // longitude / latitude offset from the anchor; callers take a short form
 // only where it equals the general one bit for bit.
-template <bool LON, bool LAT, int SPL, bool FULL>
+template <typename PT, bool LON, bool LAT, int SPL, bool FULL>
 __device__ __forceinline__ float warp_samples(const SweepArgs &A, const Patch<SPL> &pt, const ViewSetup &V,
                                               __amdgpu_buffer_rsrc_t img, int last, float s[SPL])
 {
@@ -633,8 +706,10 @@ __device__ __forceinline__ float warp_samples(const SweepArgs &A, const Patch<SP
         // storage; the clamp only keeps every address there whatever the
         // inputs
         const int off = clamp0_int(
-            (int)(((unsigned)(__mul24(floor_int(vl), A.Wp) + floor_int(ul)) << 4) + (unsigned)V.base), last);
-        s[i] = bilinear(img, off, au, av);
+            (int)(((unsigned)(__mul24(floor_int(vl), A.Wp) + floor_int(ul)) << cell_shift<PT>()) +
+                  (unsigned)V.base),
+            last);
+        s[i] = bilinear<PT>(img, off, au, av);
         sum += FULL ? s[i] : s[i] * pt.wt[i];
     }
     return sum;
@@ -658,11 +733,35 @@ __device__ __forceinline__ float warp_samples(const SweepArgs &A, const Patch<SP
 // >= bound the remaining views are skipped and a value >= bound returned.
 // Float addition and multiplication by fl(1/top_k) round monotonically, so
 // every decision the caller takes is the one the full evaluation gives.
-template <typename PT, int LPP, int SPL, bool FULL, bool VIEWS>
+// Work a half-sweep actually executes, counted per pixel when the launch
+// asks for it (instrumentation only; the decisions are the same either way).
+enum WorkField {
+    WC_PIXELS,        // pixel updates
+    WC_PROP,          // propagation candidates considered (offsets)
+    WC_TRIALS,        // refinement trials considered
+    WC_SKIP_GEOMETRY, // candidates dropped before scoring: neighbour outside
+                      // the band or invalid, plane behind the pixel's ray or
+                      // its depth out of range, refined normal not facing
+    WC_SKIP_REPEAT,   // propagation candidates equal to the current plane or
+                      // to the previous candidate (same cost, cannot win)
+    WC_SCORED,        // candidates scored (evaluate calls)
+    WC_FACING,        // scored planes not facing every sample ray (cost 2,
+                      // no view evaluated)
+    WC_VIEWS,         // (pixel, candidate, view) NCC evaluations executed
+    WC_PRUNED,        // views skipped by the top-k bound
+    WC_FIELDS
+};
+struct WorkCount {
+    unsigned v[WC_FIELDS];
+};
+
+template <typename PT, int LPP, int SPL, bool FULL, bool VIEWS, bool COUNT = false>
 __device__ __forceinline__ float evaluate(const SweepArgs &A, const Patch<SPL> &pt, float d,
                                           float n0, float n1, float n2, int lane,
-                                          long long out_index, float bound = 3.0f)
+                                          long long out_index, float bound = 3.0f,
+                                          WorkCount *wc = nullptr)
 {
+    if (COUNT) wc->v[WC_SCORED]++;
     const double n64[3] = {(double)n0, (double)n1, (double)n2};
     const double nbp = n64[0] * pt.bp64[0] + n64[1] * pt.bp64[1] + n64[2] * pt.bp64[2];
     const double c64 = (double)d * nbp;
@@ -684,9 +783,9 @@ __device__ __forceinline__ float evaluate(const SweepArgs &A, const Patch<SPL> &
     if (!ok) {
         if (VIEWS && lane == 0)
             for (int j = 0; j < A.n_views; ++j) A.view_out[j][out_index] = 2.0f;
+        if (COUNT) wc->v[WC_FACING]++;
         return 2.0f;
     }
-    static_assert(sizeof(PT) == 16, "sample offsets are formed as cell index << 4");
     // the offset of the last cell
     const int last = A.pad_bytes - (int)sizeof(PT);
     // the top_k smallest view costs, ascending, as bit patterns: costs are
@@ -703,13 +802,14 @@ __device__ __forceinline__ float evaluate(const SweepArgs &A, const Patch<SPL> &
             // sample loops)
             const double nbp_r = (double)n0 * pt.bp64[0] + (double)n1 * pt.bp64[1] + (double)n2 * pt.bp64[2];
             ViewSetup mine;
-            view_setup<LPP, SPL>(A, pt, jb + lane, -((double)d * nbp_r), nbp_r, n0, n1, n2, mine);
+            view_setup<LPP, SPL, cell_shift<PT>()>(A, pt, jb + lane, -((double)d * nbp_r), nbp_r, n0, n1, n2, mine);
             put_setup(setup_lds, threadIdx.x, mine);
         }
         __builtin_amdgcn_wave_barrier();
         const int nr = min(LPP, A.n_views - jb);
         for (int t = 0; t < nr; ++t) {
             const int j = jb + t;
+            if (COUNT) wc->v[WC_VIEWS]++;
             ViewSetup V;
             get_setup(setup_lds, slot0 + t, V);
             const __amdgpu_buffer_rsrc_t img = make_rsrc(A.pad[j], A.pad_bytes);
@@ -717,11 +817,11 @@ __device__ __forceinline__ float evaluate(const SweepArgs &A, const Patch<SPL> &
             float sum;
             if (__all(V.short_ok & SHORT_LAT)) {
                 if (__all(V.short_ok & SHORT_LON))
-                    sum = warp_samples<true, true, SPL, FULL>(A, pt, V, img, last, s);
+                    sum = warp_samples<PT, true, true, SPL, FULL>(A, pt, V, img, last, s);
                 else
-                    sum = warp_samples<false, true, SPL, FULL>(A, pt, V, img, last, s);
+                    sum = warp_samples<PT, false, true, SPL, FULL>(A, pt, V, img, last, s);
             } else {
-                sum = warp_samples<false, false, SPL, FULL>(A, pt, V, img, last, s);
+                sum = warp_samples<PT, false, false, SPL, FULL>(A, pt, V, img, last, s);
             }
             sum = group_sum<LPP>(sum);
             const float ms = sum * A.inv_P;
@@ -736,7 +836,7 @@ __device__ __forceinline__ float evaluate(const SweepArgs &A, const Patch<SPL> &
             cv = group_sum<LPP>(cv);
             const float vs = m2 * A.inv_P, cov = cv * A.inv_P;
             float cj;
-            if (pt.var_r < A.var_floor || vs < A.var_floor) {
+            if (pt.var_r < A.var_floor || vs < A.var_floor_s) {
                 cj = 2.0f;
             } else {
                 float ncc = cov * __builtin_amdgcn_rsqf(pt.var_r * vs);
@@ -771,7 +871,10 @@ __device__ __forceinline__ float evaluate(const SweepArgs &A, const Patch<SPL> &
                         if (i >= have) break;
                         lb += __uint_as_float(top[i]);
                     }
-                    if (lb * A.inv_k >= bound) return lb * A.inv_k;
+                    if (lb * A.inv_k >= bound) {
+                        if (COUNT) wc->v[WC_PRUNED] += A.n_views - 1 - j;
+                        return lb * A.inv_k;
+                    }
                 }
             }
         }
@@ -843,6 +946,7 @@ struct Launch {
     const Entry *entries;   // n_entries + 1 entries
     int n_entries;
     int slots;              // workgroup slots per XCD; the grid is 8 * slots
+    unsigned long long *counts;  // half-sweeps: work counters, or null
 };
 
 // The tables are written before a launch and only read by it: reading them
@@ -940,6 +1044,55 @@ __device__ __forceinline__ void pad_one(const PadJob &J, long long i)
     static_cast<float4 *>(J.dst)[i] = make_float4(a, b - a, e - a, (f - e) - (b - a));
 }
 
+// FP16 images: the four corner halves, copied.
+__device__ __forceinline__ unsigned half_bits(const ImgRef &im, int x, int y)
+{
+    return reinterpret_cast<const unsigned short *>(static_cast<const char *>(im.ptr) + (long long)y * im.pitch)[x];
+}
+
+__device__ __forceinline__ void pad_one_f16(const PadJob &J, long long i)
+{
+    const int py = (int)(i / J.Wp), px = (int)(i - (long long)py * J.Wp);
+    int sx = px - (J.W >> 1) - 2;
+    sx = sx < 0 ? sx + J.W : sx;
+    sx = sx >= J.W ? sx - J.W : sx;
+    const int sx1 = sx + 1 == J.W ? 0 : sx + 1;
+    const int r0 = py == 0 ? 0 : py - 1;
+    const int r1 = py >= J.H ? J.H - 1 : py;
+    Cell8 c;
+    c.ab = half_bits(J.src, sx, r0) | half_bits(J.src, sx1, r0) << 16;
+    c.ef = half_bits(J.src, sx, r1) | half_bits(J.src, sx1, r1) << 16;
+    static_cast<Cell8 *>(J.dst)[i] = c;
+}
+
+// 8-bit images: corner and differences of the raw values, as halves.
+__device__ __forceinline__ int raw_u8(const ImgRef &im, int x, int y)
+{
+    return (static_cast<const uint8_t *>(im.ptr) + (long long)y * im.pitch)[x];
+}
+
+__device__ __forceinline__ unsigned half_of_int(int v)
+{
+    return __builtin_bit_cast(unsigned short, (_Float16)(float)v);
+}
+
+__device__ __forceinline__ void pad_one_u8(const PadJob &J, long long i)
+{
+    const int py = (int)(i / J.Wp), px = (int)(i - (long long)py * J.Wp);
+    int sx = px - (J.W >> 1) - 2;
+    sx = sx < 0 ? sx + J.W : sx;
+    sx = sx >= J.W ? sx - J.W : sx;
+    const int sx1 = sx + 1 == J.W ? 0 : sx + 1;
+    const int r0 = py == 0 ? 0 : py - 1;
+    const int r1 = py >= J.H ? J.H - 1 : py;
+    const int a = raw_u8(J.src, sx, r0), b = raw_u8(J.src, sx1, r0);
+    const int e = raw_u8(J.src, sx, r1), f = raw_u8(J.src, sx1, r1);
+    Cell8d c;
+    c.lo = half_of_int(a) | half_of_int(b - a) << 16;
+    c.hi = half_of_int(e - a) | half_of_int((f - e) - (b - a)) << 16;
+    static_cast<Cell8d *>(J.dst)[i] = c;
+}
+
 __global__ __launch_bounds__(BLOCK) void k_pad(Launch L)
 {
     int e, local;
@@ -948,8 +1101,8 @@ __global__ __launch_bounds__(BLOCK) void k_pad(Launch L)
     const PadJob &J = *const_view<PadJob>(L.table, E.job);
     const long long i = (long long)local * BLOCK + threadIdx.x;
     if (i >= (long long)(J.H + 1) * J.Wp) return;
-    if (J.dtype == DT_F16) pad_one<__half>(J, i);
-    else if (J.dtype == DT_U8) pad_one<uint8_t>(J, i);
+    if (J.dtype == DT_F16) pad_one_f16(J, i);
+    else if (J.dtype == DT_U8) pad_one_u8(J, i);
     else pad_one<float>(J, i);
 }
 
@@ -1064,8 +1217,9 @@ __device__ __forceinline__ void init_tile(const SweepArgs &A, int tile)
 // One half-sweep (Sec. III-C): propagation from the opposite-colour
 // neighbourhood, then random refinement; strictly cheaper candidates win, the
 // first in table order on ties. Pixels of the other colour are only read.
-template <int DT, int LPP, int SPL, bool FULL>
-__device__ __forceinline__ void halfsweep_tile(const SweepArgs &A, int tile, int iteration, int colour)
+template <int DT, int LPP, int SPL, bool FULL, bool COUNT = false>
+__device__ __forceinline__ void halfsweep_tile(const SweepArgs &A, int tile, int iteration, int colour,
+                                               WorkCount *wc = nullptr)
 {
     using TR = typename Storage<DT>::ref_t;
     using PT = typename Storage<DT>::pad_t;
@@ -1079,6 +1233,11 @@ __device__ __forceinline__ void halfsweep_tile(const SweepArgs &A, int tile, int
     // (32 bits: images hold fewer than 2^31 pixels; one register less to
     // keep through the evaluations)
     const unsigned idx = (unsigned)y * (unsigned)A.W + (unsigned)x;
+    if (COUNT) {
+        wc->v[WC_PIXELS] = 1;
+        wc->v[WC_PROP] = A.n_offsets;
+        wc->v[WC_TRIALS] = A.refine_trials;
+    }
 
     Patch<SPL> pt;
     patch_setup<TR, LPP, SPL>(A, x, y, lane, pt);
@@ -1096,16 +1255,28 @@ __device__ __forceinline__ void halfsweep_tile(const SweepArgs &A, int tile, int
         int qx = x + A.off_x[o];
         qx = qx < 0 ? qx + A.W : (qx >= A.W ? qx - A.W : qx);
         const int qy = y + A.off_y[o];
-        if (qy < A.r || qy > A.H - 1 - A.r) continue;
+        if (qy < A.r || qy > A.H - 1 - A.r) {
+            if (COUNT) wc->v[WC_SKIP_GEOMETRY]++;
+            continue;
+        }
         const float4 sq = A.state[(long long)qy * A.W + qx];
-        if (!(sq.w > 0.0f)) continue;
+        if (!(sq.w > 0.0f)) {
+            if (COUNT) wc->v[WC_SKIP_GEOMETRY]++;
+            continue;
+        }
         float bq[3];
         bearing(A, qx, qy, bq);
         const float cq = sq.w * (sq.x * bq[0] + sq.y * bq[1] + sq.z * bq[2]);
         const float den = sq.x * pt.bp[0] + sq.y * pt.bp[1] + sq.z * pt.bp[2];
-        if (!(den < 0.0f)) continue;
+        if (!(den < 0.0f)) {
+            if (COUNT) wc->v[WC_SKIP_GEOMETRY]++;
+            continue;
+        }
         const float dd = cq * __builtin_amdgcn_rcpf(den);
-        if (!(dd >= A.dmin && dd <= A.dmax)) continue;
+        if (!(dd >= A.dmin && dd <= A.dmax)) {
+            if (COUNT) wc->v[WC_SKIP_GEOMETRY]++;
+            continue;
+        }
         // (the stored cost of the current plane is this evaluation's result
         // only when these kernels computed it)
         const bool same_best = (A.own_costs || !loaded) &&
@@ -1113,12 +1284,15 @@ __device__ __forceinline__ void halfsweep_tile(const SweepArgs &A, int tile, int
                                __float_as_uint(sq.y) == __float_as_uint(bn1) && __float_as_uint(sq.z) == __float_as_uint(bn2);
         const bool same_prev = __float_as_uint(dd) == __float_as_uint(pd) && __float_as_uint(sq.x) == __float_as_uint(pn0) &&
                                __float_as_uint(sq.y) == __float_as_uint(pn1) && __float_as_uint(sq.z) == __float_as_uint(pn2);
-        if (same_best || same_prev) continue;
+        if (same_best || same_prev) {
+            if (COUNT) wc->v[WC_SKIP_REPEAT]++;
+            continue;
+        }
         pd = dd;
         pn0 = sq.x;
         pn1 = sq.y;
         pn2 = sq.z;
-        const float c = evaluate<PT, LPP, SPL, FULL, false>(A, pt, dd, sq.x, sq.y, sq.z, lane, 0, bc);
+        const float c = evaluate<PT, LPP, SPL, FULL, false, COUNT>(A, pt, dd, sq.x, sq.y, sq.z, lane, 0, bc, wc);
         if (c < bc) {
             bc = c;
             bd = dd;
@@ -1159,13 +1333,19 @@ __device__ __forceinline__ void halfsweep_tile(const SweepArgs &A, int tile, int
         float m1 = fmaf(A.sn[t], 2.0f * u[2] - 1.0f, bn1);
         float m2 = fmaf(A.sn[t], 2.0f * u[3] - 1.0f, bn2);
         const float len2 = m0 * m0 + m1 * m1 + m2 * m2;
-        if (!(len2 > 0.0f)) continue;
+        if (!(len2 > 0.0f)) {
+            if (COUNT) wc->v[WC_SKIP_GEOMETRY]++;
+            continue;
+        }
         const float il = __builtin_amdgcn_rsqf(len2);
         m0 *= il;
         m1 *= il;
         m2 *= il;
-        if (!(m0 * pt.bp[0] + m1 * pt.bp[1] + m2 * pt.bp[2] < 0.0f)) continue;
-        const float c = evaluate<PT, LPP, SPL, FULL, false>(A, pt, dd, m0, m1, m2, lane, 0, bc);
+        if (!(m0 * pt.bp[0] + m1 * pt.bp[1] + m2 * pt.bp[2] < 0.0f)) {
+            if (COUNT) wc->v[WC_SKIP_GEOMETRY]++;
+            continue;
+        }
+        const float c = evaluate<PT, LPP, SPL, FULL, false, COUNT>(A, pt, dd, m0, m1, m2, lane, 0, bc, wc);
         if (c < bc) {
             bc = c;
             bd = dd;
@@ -1174,6 +1354,8 @@ __device__ __forceinline__ void halfsweep_tile(const SweepArgs &A, int tile, int
             bn2 = m2;
         }
     }
+    if (COUNT && lane != 0)
+        for (int f = 0; f < WC_FIELDS; ++f) wc->v[f] = 0;
     if (lane == 0) {
         A.state[idx] = make_float4(bn0, bn1, bn2, bd);
         A.cost[idx] = bc;
@@ -1227,6 +1409,28 @@ __global__ __launch_bounds__(BLOCK) PMS_OCCUPANCY(KIND, SPL) void k_tiles(Launch
     if (KIND == TK_INIT) init_tile<DT, LPP, SPL, FULL>(A, local);
     else if (KIND == TK_HALFSWEEP) halfsweep_tile<DT, LPP, SPL, FULL>(A, local, E.iteration, E.colour);
     else eval_tile<DT, LPP, SPL, FULL>(A, local);
+}
+
+// The half-sweep with its executed work counted: per workgroup the pixels'
+// counts are summed in LDS and added to L.counts (WC_FIELDS 64-bit
+// counters) with one atomic per field.
+template <int DT, int LPP, int SPL, bool FULL>
+__global__ __launch_bounds__(BLOCK) PMS_OCCUPANCY(TK_HALFSWEEP, SPL) void k_halfsweep_counted(Launch L)
+{
+    __shared__ unsigned wg[WC_FIELDS];
+    int e, local;
+    if (!block_entry(L, e, local)) return;
+    if (threadIdx.x < WC_FIELDS) wg[threadIdx.x] = 0;
+    const Entry &E = *const_view<Entry>(L.entries, e);
+    const SweepArgs &A = const_view<JobArgs>(L.table, E.job)->s;
+    stage_poses(A);  // (its barrier also orders the zeroing above)
+    WorkCount wc;
+    for (int f = 0; f < WC_FIELDS; ++f) wc.v[f] = 0;
+    halfsweep_tile<DT, LPP, SPL, FULL, true>(A, local, E.iteration, E.colour, &wc);
+    for (int f = 0; f < WC_FIELDS; ++f)
+        if (wc.v[f]) atomicAdd(&wg[f], wc.v[f]);
+    __syncthreads();
+    if (threadIdx.x < WC_FIELDS) atomicAdd(&L.counts[threadIdx.x], (unsigned long long)wg[threadIdx.x]);
 }
 
 // Caller planes from the plane state (invalid pixels: depth and normal 0,

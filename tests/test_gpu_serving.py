@@ -77,7 +77,8 @@ def test_admission_respects_the_arena(pms, pool):
     H = W // 2
     mjs = [synth.MixedJob(W, 3, [1, 2, 4, 5], seed=k) for k in range(5)]
     state = H * W * (16 + 4 + 8)
-    pad = (H + 1) * (2 * W + 4) * 16  # re-laid-out copies: 16-byte bilinear cells
+    assert pool[W].dtype == "f16"
+    pad = (H + 1) * (2 * W + 4) * 8  # re-laid-out copies: 8-byte cells of four FP16 corners
     # the four shared neighbour copies and room for two jobs' state, not three
     arena = int(2.5 * state) + 4 * pad + (64 << 10)
     server = pms.Server(arena_bytes=max(arena, 1 << 20), max_jobs=8, ctx=ctx)
