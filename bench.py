@@ -418,6 +418,14 @@ def quality_section(args, torch, pms, synth, ctx) -> dict:
         step()
     torch.cuda.synchronize()
     t = (time.perf_counter() - t0) / K
+    # executed work of one more (untimed) step, by the counting half-sweep
+    ctx.work_count_enable(True)
+    step()
+    counts = ctx.work_count_read()
+    ctx.work_count_enable(False)
+    hyps = len(params["offsets"]) + params["refine_trials"]
+    nominal = counts["pixels"] * hyps * len(w.nbrs)
+    P = patch_samples(params)
     r = (params["patch_size"] - 1) // 2
     comp, acc = _gt_accuracy(out[0].cpu().numpy(), w.gt_depth[w.ref], r)
     # fusion of the window's 5 depth maps (the filtered keyframe and its 4
@@ -438,6 +446,14 @@ def quality_section(args, torch, pms, synth, ctx) -> dict:
             "keyframes_per_s": 1.0 / t, "ms_per_keyframe": t * 1e3, "steps": K,
             "schedule": ctx.get_schedule(),
             "completeness": comp, "within_1pct_of_gt": acc,
+            "executed": {"ncc_evals_per_keyframe": counts["view_evals"],
+                         "executed_of_nominal": counts["view_evals"] / max(nominal, 1),
+                         "samples_per_keyframe": counts["view_evals"] * P,
+                         "ncc_evals_per_s": counts["view_evals"] / t,
+                         # at the same per-sample / per-evaluation pricing as the headline
+                         "valu_frac_contract_pricing": counts["view_evals"] * (P * SLOTS_PER_SAMPLE + SLOTS_PER_EVAL)
+                                                       / t / 1e12 / PEAK_TSLOTS,
+                         "counts_per_keyframe": counts},
             "fusion": {"maps": len(depths), "valid_points": n_pts, "voxel_m": 0.02,
                        "kept_points": n_kept, "fuse_ms": fuse_ms, "coverage_ms": cov_ms,
                        "covered_fraction_720x360": n_cov / (720 * 360)}}
@@ -735,6 +751,84 @@ def _late_latency(results, after_s: float) -> dict:
             "p99": float(np.percentile(lat, 99)), "mean": float(lat.mean())}
 
 
+def _pmc_per_dispatch(d: str) -> dict:
+    """{(file, dispatch): (kernel name, {counter: value summed over its rows})}
+    of the rocprofv3 --pmc csv output under `d`."""
+    import csv
+    import glob
+    rows = {}
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            key = (f, r["Dispatch_Id"])
+            name, vals = rows.setdefault(key, (r["Kernel_Name"], {}))
+            vals[r["Counter_Name"]] = vals.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    return rows
+
+
+def util_summary(kernel: str, dirs: list) -> str:
+    """Markdown table of the per-dispatch means of every counter that
+    rocprofv3 --pmc runs (csv, one directory per pass) recorded for the
+    dispatches whose kernel name contains `kernel`, and the utilisation
+    figures derived from them (256 CUs, 1024 SIMDs, 8 XCDs)."""
+    means, n_disp = {}, {}
+    for d in dirs:
+        vals = [v for name, v in _pmc_per_dispatch(d).values() if kernel in name]
+        for c in sorted({c for v in vals for c in v}):
+            xs = [v[c] for v in vals if c in v]
+            if c == "GRBM_GUI_ACTIVE" and c in means:
+                continue
+            means[c] = sum(xs) / len(xs)
+            n_disp[c] = len(xs)
+    lines = ["| counter | per dispatch | dispatches |", "|---|---|---|"]
+    lines += [f"| {c} | {v:.4g} | {n_disp[c]} |" for c, v in means.items()]
+    m = means
+    der = []
+    cyc = m.get("GRBM_GUI_ACTIVE", 0.0) / 8.0
+    if cyc:
+        der.append(("kernel cycles per XCD (GRBM_GUI_ACTIVE / 8)", f"{cyc:.4g} ({cyc / 2.4e6:.3f} ms at 2.4 GHz)"))
+
+        def add(label, num, den):
+            if all(k in m for k in num[1]) and den:
+                der.append((label, f"{num[0] / den:.3f}"))
+        if "SQ_INSTS_VALU" in m:
+            add("VALU issue: SQ_INSTS_VALU x 4 / (1024 SIMDs x cycles)", (m["SQ_INSTS_VALU"] * 4, ["SQ_INSTS_VALU"]), 1024 * cyc)
+        if "SQ_ACTIVE_INST_VALU" in m:
+            add("VALU active: SQ_ACTIVE_INST_VALU x 4 / (1024 x cycles)", (m["SQ_ACTIVE_INST_VALU"] * 4, []), 1024 * cyc)
+            if "SQ_THREAD_CYCLES_VALU" in m:
+                add("VALU lane utilisation: SQ_THREAD_CYCLES_VALU / (SQ_ACTIVE_INST_VALU x 64)",
+                    (m["SQ_THREAD_CYCLES_VALU"], []), 64 * m["SQ_ACTIVE_INST_VALU"])
+        for c, label in (("TA_TA_BUSY_sum", "texture addresser busy"), ("TD_TD_BUSY_sum", "texture data busy"),
+                         ("TCP_PENDING_STALL_CYCLES_sum", "L1 pending-miss stall")):
+            if c in m:
+                der.append((f"{label}: {c} / (256 CUs x cycles)", f"{m[c] / (256 * cyc):.3f}"))
+        if "SQ_LDS_IDX_ACTIVE" in m:
+            der.append(("LDS indexed-access busy: SQ_LDS_IDX_ACTIVE / (256 x cycles)",
+                        f"{m['SQ_LDS_IDX_ACTIVE'] / (256 * cyc):.4f}"))
+        if "SQ_LDS_BANK_CONFLICT" in m:
+            der.append(("LDS bank-conflict stall: SQ_LDS_BANK_CONFLICT / (256 x cycles)",
+                        f"{m['SQ_LDS_BANK_CONFLICT'] / (256 * cyc):.5f}"))
+    if "SQ_LDS_BANK_CONFLICT" in m and "SQ_LDS_IDX_ACTIVE" in m and m["SQ_LDS_IDX_ACTIVE"] > m["SQ_LDS_BANK_CONFLICT"]:
+        der.append(("LDS conflict cycles per conflict-free LDS cycle: SQ_LDS_BANK_CONFLICT / "
+                    "(SQ_LDS_IDX_ACTIVE - SQ_LDS_BANK_CONFLICT)",
+                    f"{m['SQ_LDS_BANK_CONFLICT'] / (m['SQ_LDS_IDX_ACTIVE'] - m['SQ_LDS_BANK_CONFLICT']):.4f}"))
+    if "TCP_TOTAL_CACHE_ACCESSES_sum" in m and "SQ_INSTS_VMEM_RD" in m:
+        der.append(("L1 lookups per vector load: TCP_TOTAL_CACHE_ACCESSES_sum / SQ_INSTS_VMEM_RD",
+                    f"{m['TCP_TOTAL_CACHE_ACCESSES_sum'] / m['SQ_INSTS_VMEM_RD']:.1f}"))
+    if "TCP_TCC_READ_REQ_sum" in m and "TCP_TOTAL_CACHE_ACCESSES_sum" in m:
+        der.append(("L1 miss fraction: TCP_TCC_READ_REQ_sum / TCP_TOTAL_CACHE_ACCESSES_sum",
+                    f"{m['TCP_TCC_READ_REQ_sum'] / m['TCP_TOTAL_CACHE_ACCESSES_sum']:.3f}"))
+    if "SQ_WAIT_INST_ANY" in m and "SQ_WAVE_CYCLES" in m:
+        der.append(("wave cycles waiting: SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES",
+                    f"{m['SQ_WAIT_INST_ANY'] / m['SQ_WAVE_CYCLES']:.3f}"))
+    if "SQ_WAVES" in m:
+        for c, label in (("SQ_INSTS_VALU", "VALU instructions per wave"), ("SQ_INSTS_VMEM_RD", "vector loads per wave"),
+                         ("SQ_INSTS_LDS", "LDS instructions per wave")):
+            if c in m:
+                der.append((label, f"{m[c] / m['SQ_WAVES']:.0f}"))
+    lines += ["", "| derived | value |", "|---|---|"] + [f"| {a} | {b} |" for a, b in der]
+    return "\n".join(lines)
+
+
 def counter_summary(fetch_dir: str, write_dir: str, probe_bytes: int, commands: list,
                     schedule: list) -> str:
     """Writes the HBM traffic summary of the half-sweep kernel from two
@@ -855,10 +949,16 @@ def main() -> int:
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="bytes of a plain device-to-device copy run once before the "
                          "timed region, to calibrate HBM byte counters (0 = none)")
+    ap.add_argument("--util-summary", nargs="+", metavar="KERNEL_OR_DIR",
+                    help="KERNEL DIR...: print the utilisation table of the dispatches of KERNEL from "
+                         "rocprofv3 --pmc csv directories (no GPU needed) and exit")
     ap.add_argument("--counter-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "SCHEDULE"),
                     help="write the traffic summary from two rocprofv3 --pmc csv directories "
                          "(no GPU needed) and exit")
     args = ap.parse_args()
+    if args.util_summary:
+        print(util_summary(args.util_summary[0], args.util_summary[1:]))
+        return 0
     if args.counter_summary:
         fetch_dir, write_dir, sched = args.counter_summary
         cmd = ("rocprofv3 --pmc {c} --output-format csv -d gpurun_out/pmc_{c} -o pmc -- python3 "
