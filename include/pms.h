@@ -363,8 +363,11 @@ pms_status pms_view_filter(pms_context *ctx, const double centre_a[3], const dou
    `voxel` metres (floor of each world coordinate / voxel) the first in
    (map, pixel) order is kept. Writes keep_out[m * H * W + y * W + x] = 1
    for kept points, else 0 (device, n_maps * H * W bytes) and the number of
-   kept points to n_kept_out (device uint64). Voxel coordinates must lie
-   within +-2^20 (points beyond are not kept). Uses 16 bytes of context
+   kept points to n_kept_out (device uint64). Points more than 2^20 voxels
+   from the first map's camera centre along an axis are not kept (with
+   depths up to depth_max around nearby cameras this needs voxel <
+   depth_max / 2^20, i.e. 0.05 mm at 50 m); world coordinates themselves may
+   be anywhere. Uses 16 bytes of context
    scratch per slot of a hash table of at least 2 n_maps W H slots. The
    result does not depend on scheduling. */
 pms_status pms_fuse(pms_context *ctx, int32_t width, int32_t height, int32_t n_maps,

@@ -74,8 +74,9 @@ struct pms_context {
     size_t budget = 0;
     // device block of the calls that run one plan at a time: argument
     // tables first, then per-job plane state and re-laid-out images
-    void *work = nullptr;
+    void *work = nullptr;  // stream-ordered allocation (hipMallocAsync)
     size_t work_bytes = 0;
+    hipEvent_t work_used = nullptr;  // recorded after the last plan using it
     std::map<std::pair<int, int>, Tables> tables;
     Staging staging[kStagingSlots];
     int staging_next = 0;
@@ -972,28 +973,44 @@ pms_status enqueue_plan(pms_context *ctx, const Plan &P, char *dev, hipStream_t 
     return PMS_OK;
 }
 
-// Grows the context's device block to `need` bytes.
-pms_status ensure_work(pms_context *ctx, size_t need)
+// Grows the context's device block to `need` bytes, stream-ordered on `s`:
+// the old block is released after the last work that used it (the event
+// recorded behind it, whatever stream that ran on), with no host wait.
+pms_status ensure_work(pms_context *ctx, size_t need, hipStream_t s)
 {
     if (need <= ctx->work_bytes) return PMS_OK;
     if (ctx->budget && need > ctx->budget)
         return fail(ctx, PMS_ERR_BUDGET, "device memory for this call exceeds the context budget");
     hipError_t e;
     if (ctx->work) {
-        // earlier work may still use the old block
-        e = hipDeviceSynchronize();
-        if (e != hipSuccess) return hip_fail(ctx, e, "hipDeviceSynchronize");
-        (void)hipFree(ctx->work);
+        if (ctx->work_used) {
+            e = hipStreamWaitEvent(s, ctx->work_used, 0);
+            if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamWaitEvent");
+        }
+        e = hipFreeAsync(ctx->work, s);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipFreeAsync of the work block");
         ctx->work = nullptr;
         ctx->work_bytes = 0;
     }
-    e = hipMalloc(&ctx->work, need);
+    e = hipMallocAsync(&ctx->work, need, s);
     if (e != hipSuccess) {
         ctx->work = nullptr;
-        return fail(ctx, PMS_ERR_OUT_OF_MEMORY, "hipMalloc of the work block failed");
+        return fail(ctx, PMS_ERR_OUT_OF_MEMORY, "hipMallocAsync of the work block failed");
     }
     ctx->work_bytes = need;
     return PMS_OK;
+}
+
+// Records, behind the work just enqueued on `s`, that the context's block
+// is in use up to here (a later growth on any stream waits for it).
+pms_status mark_work_used(pms_context *ctx, hipStream_t s)
+{
+    if (!ctx->work_used) {
+        hipError_t e = hipEventCreateWithFlags(&ctx->work_used, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipEventCreate");
+    }
+    hipError_t e = hipEventRecord(ctx->work_used, s);
+    return e == hipSuccess ? PMS_OK : hip_fail(ctx, e, "hipEventRecord");
 }
 
 // Runs validated jobs through the context's own block on `s`.
@@ -1003,11 +1020,12 @@ pms_status run_specs(pms_context *ctx, const std::vector<JobSpec> &specs, hipStr
     if (st != PMS_OK) return st;
     Plan P;
     if ((st = build_plan(ctx, specs, nullptr, P)) != PMS_OK) return st;
-    if ((st = ensure_work(ctx, P.total_bytes)) != PMS_OK) return st;
+    if ((st = ensure_work(ctx, P.total_bytes, s)) != PMS_OK) return st;
     char *base = static_cast<char *>(ctx->work);
     if ((st = build_plan(ctx, specs, base, P)) != PMS_OK) return st;
     if ((st = upload_args(ctx, P, base, s)) != PMS_OK) return st;
-    return enqueue_plan(ctx, P, base, s);
+    if ((st = enqueue_plan(ctx, P, base, s)) != PMS_OK) return st;
+    return mark_work_used(ctx, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -1295,7 +1313,11 @@ pms_status pms_context_destroy(pms_context *ctx)
         (void)hipSetDevice(ctx->device);
         (void)hipDeviceSynchronize();
     }
-    if (ctx->work) (void)hipFree(ctx->work);
+    if (ctx->work) {
+        (void)hipFreeAsync(ctx->work, nullptr);
+        (void)hipStreamSynchronize(nullptr);
+    }
+    if (ctx->work_used) (void)hipEventDestroy(ctx->work_used);
     if (ctx->work_counts) (void)hipFree(ctx->work_counts);
     for (auto &kv : ctx->tables) (void)hipFree(kv.second.row);
     for (auto &sl : ctx->staging) {
@@ -1507,38 +1529,41 @@ pms_status pms_autotune(pms_context *ctx, const pms_job *jobs, int32_t n_jobs, i
     earlier.swap(ctx->launches);
     double best = 1e300;
     Schedule best_s = keep;
+    // times one candidate schedule; whatever happens, every event it
+    // recorded is waited for and returned to the pool
+    auto measure = [&](const Schedule &c, double *ms_out) -> pms_status {
+        ctx->sched = c;
+        ctx->profiling = false;
+        pms_status r = run_specs(ctx, specs, s);  // warm-up
+        ctx->profiling = true;
+        for (int k = 0; k < reps && r == PMS_OK; ++k) r = run_specs(ctx, specs, s);
+        ctx->profiling = false;
+        double ms = 0.0;
+        for (auto &l : ctx->launches) {
+            hipError_t e = hipEventSynchronize(l.stop);
+            if (e != hipSuccess && r == PMS_OK) r = hip_fail(ctx, e, "hipEventSynchronize");
+            float t = 0.0f;
+            if (e == hipSuccess && hipEventElapsedTime(&t, l.start, l.stop) == hipSuccess &&
+                (l.kind == KK_INIT || l.kind == KK_HALFSWEEP))
+                ms += t;
+            ctx->event_pool.push_back(l.start);
+            ctx->event_pool.push_back(l.stop);
+        }
+        ctx->launches.clear();
+        *ms_out = ms / reps;
+        return r;
+    };
     const int lanes[3] = {0, 2, 8};
-    for (int li = 0; li < (try_lanes ? 3 : 1); ++li)
-        for (int wy = 0; wy <= 4; ++wy)
-            for (int bx = 0; bx <= 2; ++bx) {
+    for (int li = 0; li < (try_lanes ? 3 : 1) && st == PMS_OK; ++li)
+        for (int wy = 0; wy <= 4 && st == PMS_OK; ++wy)
+            for (int bx = 0; bx <= 2 && st == PMS_OK; ++bx) {
                 Schedule c;
                 c.wy_log2 = wy;
                 c.bx_log2 = bx;
                 c.lpp = try_lanes ? lanes[li] : keep.lpp;
-                ctx->sched = c;
-                ctx->profiling = false;
-                if ((st = run_specs(ctx, specs, s)) != PMS_OK) break;  // warm-up
-                ctx->profiling = true;
-                for (int k = 0; k < reps && st == PMS_OK; ++k) st = run_specs(ctx, specs, s);
-                ctx->profiling = false;
-                if (st != PMS_OK) break;
                 double ms = 0.0;
-                for (auto &l : ctx->launches) {
-                    hipError_t e = hipEventSynchronize(l.stop);
-                    if (e != hipSuccess) {
-                        st = hip_fail(ctx, e, "hipEventSynchronize");
-                        break;
-                    }
-                    float t = 0.0f;
-                    (void)hipEventElapsedTime(&t, l.start, l.stop);
-                    if (l.kind == KK_INIT || l.kind == KK_HALFSWEEP) ms += t;
-                    ctx->event_pool.push_back(l.start);
-                    ctx->event_pool.push_back(l.stop);
-                }
-                ctx->launches.clear();
-                if (st != PMS_OK) break;
-                ms /= reps;
-                if (ms < best) {
+                st = measure(c, &ms);
+                if (st == PMS_OK && ms < best) {
                     best = ms;
                     best_s = c;
                 }
@@ -1689,7 +1714,8 @@ pms_status pms_warp_planes(pms_context *ctx, int32_t width, int32_t height,
     Tables T;
     if ((st = get_tables(ctx, width, height, &T)) != PMS_OK) return st;
     const long long npx = (long long)width * height;
-    if ((st = ensure_work(ctx, (size_t)npx * sizeof(unsigned long long))) != PMS_OK) return st;
+    if ((st = ensure_work(ctx, (size_t)npx * sizeof(unsigned long long), static_cast<hipStream_t>(stream))) != PMS_OK)
+        return st;
     pms::WarpArgs A;
     std::memset(&A, 0, sizeof A);
     A.W = width;
@@ -1729,7 +1755,7 @@ pms_status pms_warp_planes(pms_context *ctx, int32_t width, int32_t height,
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(ctx, e, "warp");
-    return PMS_OK;
+    return mark_work_used(ctx, s);
 }
 
 pms_status pms_view_filter(pms_context *ctx, const double centre_a[3], const double centre_b[3],
@@ -1815,8 +1841,20 @@ pms_status pms_fuse(pms_context *ctx, int32_t width, int32_t height, int32_t n_m
     const long long points = (long long)width * height * n_maps;
     unsigned long long cap = 1024;
     while (cap < 2ULL * (unsigned long long)points) cap <<= 1;
-    if ((st = ensure_work(ctx, (size_t)cap * 2 * sizeof(unsigned long long))) != PMS_OK) return st;
+    if ((st = ensure_work(ctx, (size_t)cap * 2 * sizeof(unsigned long long), static_cast<hipStream_t>(stream))) !=
+        PMS_OK)
+        return st;
     A.voxel = voxel;
+    {
+        // camera centre of the first map, -R^T t, in voxel coordinates
+        const pms_pose &P = poses[0];
+        for (int k = 0; k < 3; ++k) {
+            const double c = -(P.R[k] * P.t[0] + P.R[3 + k] * P.t[1] + P.R[6 + k] * P.t[2]);
+            A.origin[k] = std::floor(c / voxel);
+        }
+        if (!(std::fabs(A.origin[0]) < 4.0e15 && std::fabs(A.origin[1]) < 4.0e15 && std::fabs(A.origin[2]) < 4.0e15))
+            return fail(ctx, PMS_ERR_INVALID_ARG, "first camera too far from the world origin for this voxel size");
+    }
     A.slots = static_cast<unsigned long long *>(ctx->work);
     A.mask = cap - 1;
     A.keep = keep_out;
@@ -1830,7 +1868,7 @@ pms_status pms_fuse(pms_context *ctx, int32_t width, int32_t height, int32_t n_m
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(ctx, e, "fuse");
-    return PMS_OK;
+    return mark_work_used(ctx, s);
 }
 
 pms_status pms_coverage(pms_context *ctx, int32_t width, int32_t height, int32_t n_maps,

@@ -1843,6 +1843,7 @@ constexpr unsigned long long EMPTY_KEY = ~0ULL;
 struct FuseArgs {
     int W, H, n_maps;
     double voxel;
+    double origin[3];  // voxel coordinates of the first map's camera centre
     const float *depth[MAXV];
     long long pitch[MAXV];
     ViewPoseD pose[MAXV];  // world -> camera of each map
@@ -1875,13 +1876,15 @@ __device__ __forceinline__ bool fuse_point(const FuseArgs &A, int m, long long i
     return true;
 }
 
-// Voxel coordinates packed 21 bits each (offset 2^20); false beyond that.
+// Voxel coordinates relative to the first camera's voxel (an exact integer
+// difference, so voxels are the world's), packed 21 bits each (offset
+// 2^20); false beyond that.
 __device__ __forceinline__ bool voxel_key(const FuseArgs &A, const double X[3], unsigned long long &key)
 {
     key = 0ULL;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const double v = floor(X[k] / A.voxel);
+        const double v = floor(X[k] / A.voxel) - A.origin[k];
         if (!(v >= -1048576.0 && v < 1048576.0)) return false;
         key = (key << 21) | (unsigned long long)((long long)v + 1048576LL);
     }

@@ -65,3 +65,42 @@ def test_profile_names_are_the_librarys():
     names = tuple(re.findall(r'"([a-z_]+)"', block))
     assert names == bench.PROFILE_NAMES
     assert set(bench.NEXT_BYTES) <= set(names)
+
+
+def test_util_summary_means_and_derived_figures(tmp_path):
+    """Per-dispatch means over the named kernel's dispatches (rows of one
+    dispatch and counter summed), GRBM_GUI_ACTIVE taken from the first pass,
+    and the derived utilisation figures from them."""
+    import csv
+    head = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+
+    def write(d, rows):
+        d.mkdir()
+        with open(d / "pmc_counter_collection.csv", "w", newline="") as f:
+            w = csv.writer(f)
+            w.writerow(head)
+            w.writerows(rows)
+
+    k, other = "void pms::k_tiles<1, 0, 4, 9, true>(pms::Launch)", "pms::k_pad(pms::Launch)"
+    cyc = 1000.0
+    write(tmp_path / "a", [
+        [1, k, "GRBM_GUI_ACTIVE", 8 * cyc], [1, k, "SQ_INSTS_VALU", 0.5 * 1024 * cyc / 4],
+        [1, k, "SQ_INSTS_VMEM_RD", 10.0], [1, k, "SQ_WAVES", 5.0],
+        [1, k, "TCP_TOTAL_CACHE_ACCESSES_sum", 150.0], [1, k, "TCP_TOTAL_CACHE_ACCESSES_sum", 150.0],
+        [2, k, "GRBM_GUI_ACTIVE", 8 * cyc], [2, k, "SQ_INSTS_VALU", 0.7 * 1024 * cyc / 4],
+        [2, k, "SQ_INSTS_VMEM_RD", 10.0], [2, k, "SQ_WAVES", 5.0],
+        [2, k, "TCP_TOTAL_CACHE_ACCESSES_sum", 300.0],
+        [3, other, "SQ_INSTS_VALU", 1e12],
+    ])
+    write(tmp_path / "b", [
+        [1, k, "GRBM_GUI_ACTIVE", 99.0], [1, k, "SQ_LDS_IDX_ACTIVE", 0.1 * 256 * cyc],
+        [1, k, "SQ_LDS_BANK_CONFLICT", 0.02 * 256 * cyc],
+    ])
+    out = bench.util_summary("k_tiles<1, 0, 4, 9, true>", [str(tmp_path / "a"), str(tmp_path / "b")])
+    lines = {ln.split("|")[1].strip(): ln.split("|")[2].strip() for ln in out.splitlines() if ln.startswith("| ")}
+    assert float(lines["GRBM_GUI_ACTIVE"]) == 8 * cyc
+    assert lines["VALU issue: SQ_INSTS_VALU x 4 / (1024 SIMDs x cycles)"] == "0.600"
+    assert lines["L1 lookups per vector load: TCP_TOTAL_CACHE_ACCESSES_sum / SQ_INSTS_VMEM_RD"] == "30.0"
+    assert lines["LDS indexed-access busy: SQ_LDS_IDX_ACTIVE / (256 x cycles)"] == "0.1000"
+    assert lines["LDS conflict cycles per conflict-free LDS cycle: SQ_LDS_BANK_CONFLICT / "
+                 "(SQ_LDS_IDX_ACTIVE - SQ_LDS_BANK_CONFLICT)"] == "0.2500"

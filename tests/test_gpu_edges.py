@@ -176,3 +176,33 @@ def test_zero_baseline_costs(pms):
                              n.astype(np.float64))
     both = (c < 2.0) & (co < 2.0)
     assert np.abs(c[both] - co[both]).max() <= 1e-4
+
+
+def test_work_block_grows_on_another_stream_without_a_host_wait(pms):
+    """A context's device block grows stream-ordered: a small call on one
+    stream, then at once (no synchronisation) a larger one on another stream
+    of the same context, give the results of a fresh context for each."""
+    small = synth.scaled("box_room", 96, seed=4)
+    large = synth.scaled("hall", 256, seed=4)
+    ctx = pms.Context(0)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    outs = []
+    for w, st in ((small, s1), (large, s2)):
+        imgs = [torch.from_numpy(a).cuda() for a in w.images]
+        torch.cuda.synchronize()
+        params = dict(w.params, iterations=2)
+        say(f"densify {w.W}x{w.H} on its own stream, no host wait")
+        with torch.cuda.stream(st):
+            o = pms.densify(imgs[w.ref], [imgs[i] for i in w.nbrs], w.poses[w.ref],
+                            [w.poses[i] for i in w.nbrs], params, ctx=ctx, stream=st)
+        outs.append((w, imgs, params, o))
+    torch.cuda.synchronize()
+    for w, imgs, params, o in outs:
+        fresh = pms.Context(0)
+        ref = pms.densify(imgs[w.ref], [imgs[i] for i in w.nbrs], w.poses[w.ref],
+                          [w.poses[i] for i in w.nbrs], params, ctx=fresh)
+        torch.cuda.synchronize()
+        for a, b in zip(o, ref):
+            assert torch.equal(a, b)
+        fresh.close()
+    ctx.close()

@@ -53,3 +53,58 @@ def test_coverage_matches_oracle(pms):
     n_o, cover_o = oracle.coverage([d.astype(np.float64) for d in depths], poses, keep_o, poses[2])
     print(f"coverage {n_o / (720 * 360):.3f}")
     assert n_g == n_o and np.array_equal(cover_g.cpu().numpy(), cover_o)
+
+
+def _shifted(poses, offset):
+    """The same cameras in a world frame moved by `offset` (metres)."""
+    o = np.asarray(offset, dtype=np.float64)
+    return [(np.asarray(R), np.asarray(t) - np.asarray(R) @ o) for R, t in poses]
+
+
+def test_keep_masks_match_oracle_far_from_the_world_origin(pms):
+    """Georeferenced-size world coordinates (thousands of km, far beyond 2^20
+    voxels of 2 cm): voxels are taken relative to the first camera, so the
+    result is still the oracle's."""
+    w, depths, poses = _maps(384)
+    poses = _shifted(poses, (3.2e6, -1.5e3, -2.7e6))
+    say("fuse 4 maps 384x192 voxel 0.02, world offset of ~4000 km")
+    keep_g, n_g = pms.fuse([torch.from_numpy(d).cuda() for d in depths], poses, 0.02)
+    torch.cuda.synchronize()
+    keep_o, n_o = oracle.fuse([d.astype(np.float64) for d in depths], poses, 0.02)
+    keep_g = keep_g.cpu().numpy()
+    diff = (keep_g != keep_o).mean()
+    print(f"kept {n_o}, mask differences {diff:.2e}")
+    assert n_o > 0.1 * keep_o.size / 4
+    assert diff <= 1e-5
+
+
+def test_points_beyond_the_key_range_are_not_kept(pms):
+    """The documented limit: a point more than 2^20 voxels from the first
+    map's camera centre along an axis is not kept (the oracle, with unbounded
+    integer voxels, keeps it); every other decision is the oracle's."""
+    w, depths, poses = _maps(192)
+    voxel = 4e-6  # 2^20 voxels = 4.19 m
+    dev = [torch.from_numpy(d).cuda() for d in depths]
+    say("fuse 4 maps 192x96 with a 4 micrometre voxel")
+    keep_g, n_g = pms.fuse(dev, poses, voxel)
+    torch.cuda.synchronize()
+    keep_g = keep_g.cpu().numpy().reshape(len(depths), -1)
+    keep_o, _ = oracle.fuse([d.astype(np.float64) for d in depths], poses, voxel)
+    keep_o = keep_o.reshape(len(depths), -1)
+    # world points and their voxel offsets from the first camera's voxel
+    from helpers import bearings
+    b = bearings(w.W, w.H).reshape(3, -1)
+    R0, t0 = poses[0]
+    c0 = -np.asarray(R0).T @ np.asarray(t0)
+    org = np.floor(c0 / voxel)
+    for m, (d, (R, t)) in enumerate(zip(depths, poses)):
+        X = np.asarray(R).T @ (d.reshape(-1).astype(np.float64) * b - np.asarray(t)[:, None])
+        off = np.floor(X / voxel) - org[:, None]
+        # (a margin of 2 voxels either side of the limit for FP64 rounding)
+        valid = d.reshape(-1) > 0
+        far = (np.abs(off) >= 2 ** 20 + 2).any(0) & valid
+        near = (np.abs(off) < 2 ** 20 - 2).all(0) & valid
+        assert far.sum() > 100 and near.sum() > 100
+        assert not keep_g[m][far].any()
+        assert keep_o[m][far].any()
+        assert (keep_g[m][near] != keep_o[m][near]).mean() <= 1e-4
