@@ -17,7 +17,9 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libpmsref.so")
+# PMSREF_LIB names another build of pmsref.c (the mutation test loads
+# deliberately broken copies through it); by default the in-tree library
+LIB_PATH = os.environ.get("PMSREF_LIB") or os.path.join(_HERE, "libpmsref.so")
 
 MAX_VIEWS = 16
 MAX_OFFSETS = 16
