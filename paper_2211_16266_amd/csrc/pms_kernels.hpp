@@ -65,10 +65,11 @@ constexpr int BLOCK = 256;    // threads per workgroup (4 waves)
 // samples per lane: exactly 3 (168 VGPRs; measured at 1920x960, 4
 // neighbours: 51.3 ms per keyframe, against 54.2 ms at exactly 4 waves,
 // 59.8 ms at 2, and 58 ms when the compiler may choose between 3 and 8),
-// at least 3 for the per-view cost evaluation. 13 and 16 samples per lane: exactly 2, with
-// up to 256 VGPRs, so that the compiler issues a view's gathers together
-// before it waits for them (with room for 3 it waits after each gather: the
-// 3840x1920 8-bit courtyard then takes 1013 ms per keyframe instead of 847).
+// at least 3 for the per-view cost evaluation. 13 and 16 samples per lane:
+// exactly 2, with up to 256 VGPRs for a view's gathers in flight together
+// (at 3 waves they spill 240-330 bytes per lane, or wait after each
+// gather: the 3840x1920 8-bit courtyard then takes 1013 ms per keyframe
+// instead of 847).
 #define PMS_OCCUPANCY(KIND, SPL) \
     __attribute__((amdgpu_waves_per_eu((SPL) <= 9 ? 3 : 2, (SPL) <= 9 ? ((KIND) == TK_EVAL ? 8 : 3) : 2)))
 // Re-laid-out neighbour image: H + 1 rows of 2W + 4 bilinear cells (16 or
@@ -241,33 +242,6 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, int b
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, bytes, 0x00020000);
 }
 
-// Bilinear sample from the cell at byte offset `off` of a re-laid-out
-// neighbour image (au, av: fractions along x, y).
-template <typename PT>
-__device__ __forceinline__ float bilinear(__amdgpu_buffer_rsrc_t r, int off, float au, float av);
-
-// FP32 cell (corner value and its three differences): one 16-byte buffer
-// load and three FMAs.
-template <>
-__device__ __forceinline__ float bilinear<float4>(__amdgpu_buffer_rsrc_t r, int off, float au, float av)
-{
-    const float4 q = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
-    const float top = fmaf(au, q.y, q.x);
-    const float dv = fmaf(au, q.w, q.z);
-    return fmaf(av, dv, top);
-}
-
-// lo + t (hi - lo) for the two halves of w, as fl(t hi + fl(lo - t lo)) in
-// FP32: the compiler makes each step one v_fma_mix_f32, which reads the
-// half operand exactly.
-__device__ __forceinline__ float lerp_halves(unsigned w, float t)
-{
-    const float lo = (float)__builtin_bit_cast(_Float16, (unsigned short)(w & 0xffffu));
-    const float hi = (float)__builtin_bit_cast(_Float16, (unsigned short)(w >> 16));
-    return fmaf(t, hi, fmaf(-t, lo, lo));
-}
-
-
 // Halves of a 32-bit word as floats (exact).
 __device__ __forceinline__ float half_lo(unsigned w)
 {
@@ -278,25 +252,56 @@ __device__ __forceinline__ float half_hi(unsigned w)
     return (float)__builtin_bit_cast(_Float16, (unsigned short)(w >> 16));
 }
 
-// Cell of a corner and three differences in halves: one 8-byte buffer load
-// and three FMAs, two of them mixed (the same blend as the FP32 cell).
-template <>
-__device__ __forceinline__ float bilinear<Cell8d>(__amdgpu_buffer_rsrc_t r, int off, float au, float av)
+// lo + t (hi - lo) for the two halves of w, as fl(t hi + fl(lo - t lo)) in
+// FP32: the compiler makes each step one v_fma_mix_f32, which reads the
+// half operand exactly.
+__device__ __forceinline__ float lerp_halves(unsigned w, float t)
 {
-    const uint2 q = __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
-    const float top = fmaf(au, half_hi(q.x), half_lo(q.x));
-    const float dv = fmaf(au, half_hi(q.y), half_lo(q.y));
-    return fmaf(av, dv, top);
+    const float lo = half_lo(w), hi = half_hi(w);
+    return fmaf(t, hi, fmaf(-t, lo, lo));
 }
 
-// Cell of four corner halves: one 8-byte buffer load, six FMAs (four mixed).
+// A bilinear sample is one buffer load of the cell at byte offset `off` of a
+// re-laid-out neighbour image (load_cell) and its blend with the fractions
+// au, av along x and y (blend_cell); the two are separate so that a view's
+// gathers can all be issued before the first blend.
+template <typename PT>
+struct CellBits {
+    using type = uint2;
+};
 template <>
-__device__ __forceinline__ float bilinear<Cell8>(__amdgpu_buffer_rsrc_t r, int off, float au, float av)
+struct CellBits<float4> {
+    using type = float4;
+};
+
+template <typename PT>
+__device__ __forceinline__ typename CellBits<PT>::type load_cell(__amdgpu_buffer_rsrc_t r, int off)
 {
-    const uint2 q = __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
-    const float top = lerp_halves(q.x, au);
-    const float bot = lerp_halves(q.y, au);
-    return fmaf(av, bot, fmaf(-av, top, top));
+    if constexpr (sizeof(PT) == 16)
+        return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+    else
+        return __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+
+template <typename PT>
+__device__ __forceinline__ float blend_cell(typename CellBits<PT>::type q, float au, float av)
+{
+    if constexpr (__is_same(PT, float4)) {
+        // FP32 corner and differences: three FMAs
+        const float top = fmaf(au, q.y, q.x);
+        const float dv = fmaf(au, q.w, q.z);
+        return fmaf(av, dv, top);
+    } else if constexpr (__is_same(PT, Cell8d)) {
+        // corner and differences in halves: the same three FMAs, two mixed
+        const float top = fmaf(au, half_hi(q.x), half_lo(q.x));
+        const float dv = fmaf(au, half_hi(q.y), half_lo(q.y));
+        return fmaf(av, dv, top);
+    } else {
+        // four corner halves: six FMAs, four mixed
+        const float top = lerp_halves(q.x, au);
+        const float bot = lerp_halves(q.y, au);
+        return fmaf(av, bot, fmaf(-av, top, top));
+    }
 }
 
 __device__ __forceinline__ void bearing(const SweepArgs &A, int x, int y, float b[3])
@@ -671,6 +676,8 @@ __device__ __forceinline__ float warp_samples(const SweepArgs &A, const Patch<SP
     const float y0c = V.y0c, y2c = V.y2c, kc = V.kc, sdc = V.sdc, cdc = V.cdc;
     const float sp0 = V.sp0, cp0 = V.cp0;
     float sum = 0.0f;
+    typename CellBits<PT>::type q[SPL];
+    float fu[SPL], fv[SPL];
 #pragma unroll
     for (int i = 0; i < SPL; ++i) {
         const float bx = pt.b[i][0], by = pt.b[i][1], bz = pt.b[i][2];
@@ -709,7 +716,19 @@ __device__ __forceinline__ float warp_samples(const SweepArgs &A, const Patch<SP
             (int)(((unsigned)(__mul24(floor_int(vl), A.Wp) + floor_int(ul)) << cell_shift<PT>()) +
                   (unsigned)V.base),
             last);
-        s[i] = bilinear<PT>(img, off, au, av);
+        q[i] = load_cell<PT>(img, off);
+        fu[i] = au;
+        fv[i] = av;
+    }
+    // Every gather of the view is in flight before the first blend. With 13
+    // or 16 samples per lane the compiler would otherwise wait for each
+    // gather before issuing the next; the empty asm with a memory clobber
+    // keeps the loads above it (3840x1920 courtyard: 845 -> 808 ms per
+    // keyframe). With 9 it already issues them together.
+    if (SPL > 9) asm volatile("" ::: "memory");
+#pragma unroll
+    for (int i = 0; i < SPL; ++i) {
+        s[i] = blend_cell<PT>(q[i], fu[i], fv[i]);
         sum += FULL ? s[i] : s[i] * pt.wt[i];
     }
     return sum;
