@@ -196,6 +196,75 @@ def patch_samples(params: dict) -> int:
     return side * side
 
 
+# Cases for the oracle agreement of the benchmark's results: each section
+# registers sampled pixels of one keyframe it densified (the images as the
+# oracle reads them, poses, parameters, and the GPU's plane and cost there);
+# the CPU leg at the end scores those planes with the oracle.
+ORACLE_CASES = []
+ORACLE_SAMPLES = 4000
+
+
+def register_oracle_case(name, imgs64, ref, nbrs, poses, params, depth, normal, cost, seed=0):
+    """depth/normal/cost: the GPU's outputs as numpy arrays (H, W) / (3, H, W)."""
+    H, W = depth.shape
+    ys, xs = np.nonzero(depth > 0)
+    rng = np.random.default_rng(seed)
+    pick = rng.choice(len(ys), size=min(ORACLE_SAMPLES, len(ys)), replace=False)
+    ys, xs = ys[pick], xs[pick]
+    ORACLE_CASES.append({"name": name, "imgs": [imgs64[ref]] + [imgs64[k] for k in nbrs],
+                         "poses": [poses[ref]] + [poses[k] for k in nbrs], "params": dict(params),
+                         "ys": ys, "xs": xs, "shape": (H, W), "depth": depth[ys, xs],
+                         "normal": normal[:, ys, xs], "cost": cost[ys, xs]})
+
+
+def oracle_agreement(threads: int) -> dict:
+    """The FP64 oracle's cost of the GPU's plane at each registered case's
+    sampled pixels against the cost the GPU stored with it (Sec. III-C: the
+    aggregated 1 - NCC)."""
+    import oracle
+    out = {}
+    for c in ORACLE_CASES:
+        H, W = c["shape"]
+        d = np.zeros((H, W))
+        n = np.zeros((3, H, W))
+        d[c["ys"], c["xs"]] = c["depth"]
+        n[:, c["ys"], c["xs"]] = c["normal"]
+        imgs = c["imgs"]
+        co, _ = oracle.eval_cost(imgs[0], imgs[1:], c["poses"][0], c["poses"][1:], c["params"], d, n,
+                                 n_threads=threads)
+        co = co[c["ys"], c["xs"]]
+        g = c["cost"].astype(np.float64)
+        both = (co < 2) & (g < 2)
+        err = np.abs(co - g)[both]
+        out[c["name"]] = {"pixels": int(len(g)), "both_valid": int(both.sum()),
+                          "validity_differs": int(((co < 2) != (g < 2)).sum()),
+                          "cost_err_max": float(err.max()) if err.size else None,
+                          "cost_err_p99": float(np.quantile(err, 0.99)) if err.size else None,
+                          "within_1e-4": float((err <= 1e-4).mean()) if err.size else None}
+    return out
+
+
+def golden_depth_agreement(depth) -> dict | None:
+    """The hall_1920 PatchMatch result (seed 0, no consistency step) against
+    the FP64 oracle's stored run of the same inputs (tests/golden)."""
+    import json as _json
+    path = os.path.join(ROOT, "tests", "golden", "hall_1920_seed0.npz")
+    if not os.path.exists(path):
+        return None
+    g = np.load(path, allow_pickle=False)
+    meta = _json.loads(str(g["meta"]))
+    code = g["depth_code"].astype(np.float64)
+    dc = meta["depth_code"]
+    lo, hi = np.log(dc["d_min"]), np.log(dc["d_max"])
+    do = np.where(code > 0, np.exp(lo + (code - 1.0) / dc["code_max"] * (hi - lo)), 0.0)
+    valid = do > 0
+    rel = np.abs(depth[valid] - do[valid]) / do[valid]
+    return {"source": "stored FP64 oracle run, tests/golden/hall_1920_seed0.npz",
+            "oracle_valid_pixels": int(valid.sum()),
+            "within_0.5pct": float((rel <= 0.005).mean()), "within_0.1pct": float((rel <= 0.001).mean()),
+            "median_rel_err": float(np.median(rel)), "validity_differs": int(((depth > 0) != valid).sum())}
+
+
 def cpu_baseline(w, params, budget_s: float, threads: int) -> dict:
     """The oracle, as it stands, on a bounded sample of the same workload:
     red half-sweeps over successive 32-row bands of the same keyframe,
@@ -447,6 +516,8 @@ def quality_section(args, torch, pms, synth, ctx) -> dict:
     P = patch_samples(params)
     r = (params["patch_size"] - 1) // 2
     comp, acc = _gt_accuracy(out[0].cpu().numpy(), w.gt_depth[w.ref], r)
+    register_oracle_case("courtyard_3840", [np.asarray(a, dtype=np.float64) for a in w.images_f32()],
+                         w.ref, w.nbrs, w.poses, params, *(t.cpu().numpy() for t in out))
     # fusion of the window's 5 depth maps (the filtered keyframe and its 4
     # map keyframes) into one de-duplicated cloud, and its panorama coverage
     depths, poses = [out[0]] + maps, [rp] + map_poses
@@ -487,6 +558,7 @@ def batch_section(args, torch, pms, synth, pool, ctx) -> dict:
     # FP32 renders for the plain path, the same rounded to FP16 for the batch
     imgs32 = {W: [torch.from_numpy(a).to(dev) for a in w.images] for W, w in pool.items()}
     imgs16 = {W: [t.half() for t in ts] for W, ts in imgs32.items()}
+    imgs16_np = {W: [t.cpu().numpy() for t in ts] for W, ts in imgs16.items()}
 
     def jobs_for(imgs):
         out = []
@@ -547,6 +619,11 @@ def batch_section(args, torch, pms, synth, pool, ctx) -> dict:
             a32.append(a)
             both = (d16 > 0) & (d32 > 0)
             agree.append(float((np.abs(d16[both] - d32[both]) <= 0.005 * d32[both]).mean()))
+        k0 = sel[0]
+        register_oracle_case(f"batch_fp16_{W}x{W // 2}",
+                             [np.asarray(a, dtype=np.float64) for a in imgs16_np[W]], mix[k0].ref,
+                             mix[k0].nbrs, pool[W].poses, jobs16[k0].params,
+                             *(t.cpu().numpy() for t in jobs16[k0].out))
         per_class[f"{W}x{W // 2}"] = {
             "jobs": len(sel),
             "fp16_batch": {"completeness": float(np.mean(c16)), "within_1pct_of_gt": float(np.mean(a16))},
@@ -1079,6 +1156,12 @@ def main() -> int:
     step()
     counts = ctx.work_count_read()
     ctx.work_count_enable(False)
+    # the PatchMatch result alone (no consistency step), untimed, for the
+    # agreement with the FP64 oracle
+    pm = [t.cpu().numpy() for t in pms.densify(ref, nbrs, rp, nps, params, ctx=ctx)]
+    golden = golden_depth_agreement(pm[0]) if args.seed == 0 else None
+    imgs64 = [np.asarray(a, dtype=np.float64) for a in w.images_f32()]
+    register_oracle_case("hall_1920", imgs64, w.ref, w.nbrs, w.poses, params, *pm)
 
     wall = t1 - t0
     kfps = K / wall
@@ -1128,6 +1211,7 @@ def main() -> int:
         "accuracy": dict(zip(("completeness", "within_1pct_of_gt"),
                              _gt_accuracy(out[0].cpu().numpy(), w.gt_depth[w.ref],
                                           (params["patch_size"] - 1) // 2))),
+        "oracle_depth_agreement": golden,
         "ncc_evals_per_s": evals_per_kf * kfps,
         "kernels_ms_per_step": {k: v[1] / K for k, v in kern.items()},
         "roofline": {
@@ -1204,6 +1288,9 @@ def main() -> int:
         log(f"cpu baseline: oracle on {threads} threads ({cpu_model()}, nproc {os.cpu_count()}), "
             f"~{args.cpu_budget:.0f} s")
         result["cpu_baseline"] = cpu_baseline(w, params, args.cpu_budget, threads)
+        log(f"oracle agreement: the oracle scores the GPU's planes at {ORACLE_SAMPLES} pixels "
+            f"of {len(ORACLE_CASES)} keyframes")
+        result["oracle_agreement"] = oracle_agreement(threads)
     else:
         result["cpu_baseline"] = None
     print(json.dumps(result), flush=True)
