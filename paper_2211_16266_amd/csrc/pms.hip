@@ -528,6 +528,11 @@ void add_rec(Plan &P, int kind, int sub, int dtype, Variant v,
 }
 
 long long blocks_of(long long n) { return (n + pms::BLOCK - 1) / pms::BLOCK; }
+// workgroups of the median filter: one per MED_TW x MED_TH tile
+int median_tiles(int W, int H)
+{
+    return ((W + pms::MED_TW - 1) / pms::MED_TW) * ((H + pms::MED_TH - 1) / pms::MED_TH);
+}
 // grid of a counting kernel over n items (at least one workgroup: every
 // workgroup adds its count, zero included, after a barrier)
 unsigned count_grid(long long n) { return (unsigned)std::max(1LL, std::min(blocks_of(n), (long long)pms::COUNT_GRID)); }
@@ -787,7 +792,7 @@ pms_status build_plan(pms_context *ctx, const std::vector<JobSpec> &specs, char 
         Items items;
         for (int i = 0; i < n; ++i)
             if (specs[i].mode == MODE_DENSIFY && specs[i].p->median_radius > 0)
-                items.emplace_back(i, (int)blocks_of((long long)specs[i].W * specs[i].H), 0, 0);
+                items.emplace_back(i, median_tiles(specs[i].W, specs[i].H), 0, 0);
         add_rec(P, KK_MEDIAN, 0, 0, none, items);
     }
     for (int i = 0; i < n; ++i)
@@ -2422,7 +2427,7 @@ pms_status pms_server_step(pms_server *S, void *stream, int32_t *active_out, int
         for (ServerJob *J : finishing) {
             const int blocks = (int)blocks_of((long long)J->spec.W * J->spec.H);
             fin.emplace_back(J->slot, blocks, 0, 0);
-            if (J->params.median_radius > 0) med.emplace_back(J->slot, blocks, 0, 0);
+            if (J->params.median_radius > 0) med.emplace_back(J->slot, median_tiles(J->spec.W, J->spec.H), 0, 0);
             if (J->job.n_maps > 0) geo.emplace_back(J->slot, blocks, 0, 0);
         }
         add_rec(P, KK_FINALIZE, 0, 0, none, fin);

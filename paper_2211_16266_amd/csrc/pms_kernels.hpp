@@ -1503,43 +1503,46 @@ __device__ __forceinline__ void median_reject(const IoArgs &A, int x, int y, flo
     }
 }
 
-__device__ __forceinline__ void median_one(const IoArgs &A, long long i)
+// Lower median of up to 25 window values (0 = invalid; n valid): sorted
+// in registers as bit patterns (positive floats order like their bits),
+// invalid ones as +inf so that they sort last, through Batcher's odd-even
+// merge sorting network for 32 slots restricted to its 140 comparators
+// among the first 25 (each dropped one would compare a slot with a +inf
+// slot above it and change nothing; the restricted network sorts all 2^25
+// zero-one inputs). Returns the bit pattern of the ((n - 1) / 2)-th
+// smallest.
+__device__ __forceinline__ unsigned lower_median25(const float v[25], int n)
 {
-    const int y = (int)(i / A.W), x = (int)(i - (long long)y * A.W);
-    const float d = state_depth(A, x, y);
-    if (!(d > 0.0f)) return;
+    const int k = (n - 1) / 2;
+    unsigned u[25];
+#pragma unroll
+    for (int q = 0; q < 25; ++q) u[q] = v[q] > 0.0f ? __float_as_uint(v[q]) : 0x7f800000u;
+#pragma unroll
+    for (int p = 1; p < 32; p <<= 1)
+#pragma unroll
+        for (int kk = p; kk >= 1; kk >>= 1)
+#pragma unroll
+            for (int j = kk % p; j + kk < 32; j += 2 * kk)
+#pragma unroll
+                for (int i = 0; i < kk; ++i) {
+                    const int a = i + j, b = i + j + kk;
+                    if (b < 25 && a / (2 * p) == b / (2 * p)) {
+                        const unsigned lo = min(u[a], u[b]), hi = max(u[a], u[b]);
+                        u[a] = lo;
+                        u[b] = hi;
+                    }
+                }
+    unsigned m = u[0];
+#pragma unroll
+    for (int q = 1; q < 13; ++q) m = q == k ? u[q] : m;
+    return m;
+}
+
+// Windows wider than 5x5: read from the plane state, the k-th smallest by
+// bisection on the bit pattern.
+__device__ __forceinline__ void median_wide(const IoArgs &A, int x, int y, float d)
+{
     const int R = A.median_radius;
-    if (R <= 2) {
-        // windows up to 5x5 (the default) are read once into registers;
-        // a window pixel outside the image or the valid band counts as 0
-        float v[25];
-        int n = 0;
-#pragma unroll
-        for (int dy = -2; dy <= 2; ++dy)
-#pragma unroll
-            for (int dx = -2; dx <= 2; ++dx) {
-                const int yy = y + dy;
-                int xx = x + dx;
-                xx = xx < 0 ? xx + A.W : (xx >= A.W ? xx - A.W : xx);
-                const bool in = abs(dy) <= R && abs(dx) <= R && yy >= 0 && yy < A.H;
-                // (the row is clamped so that the read stays in the image)
-                const float vv = state_depth(A, xx, min(max(yy, 0), A.H - 1));
-                v[(dy + 2) * 5 + dx + 2] = in ? vv : 0.0f;
-                n += in && vv > 0.0f ? 1 : 0;
-            }
-        const int k = (n - 1) / 2;
-        unsigned lo = 1u, hi = 0x7f800000u;
-        while (lo < hi) {
-            const unsigned mid = lo + ((hi - lo) >> 1);
-            int c = 0;
-#pragma unroll
-            for (int q = 0; q < 25; ++q) c += (v[q] > 0.0f && __float_as_uint(v[q]) <= mid) ? 1 : 0;
-            if (c > k) hi = mid;
-            else lo = mid + 1;
-        }
-        median_reject(A, x, y, d, lo);
-        return;
-    }
     const int y0 = max(y - R, 0), y1 = min(y + R, A.H - 1);
     int n = 0;
     for (int yy = y0; yy <= y1; ++yy)
@@ -1566,14 +1569,55 @@ __device__ __forceinline__ void median_one(const IoArgs &A, long long i)
     median_reject(A, x, y, d, lo);
 }
 
+// One workgroup per tile of MED_TW x MED_TH pixels. Windows up to 5x5 (the
+// default) read the tile's depths and a 2-pixel halo from LDS: staged once
+// per tile from the plane state, the longitude wrapping around the seam,
+// rows beyond the image and outside the valid band as 0; each pixel then
+// takes its 25 values from LDS into registers.
+constexpr int MED_TW = 64, MED_TH = 4;
+static_assert(MED_TW * MED_TH == BLOCK, "one pixel per thread");
+
 __global__ __launch_bounds__(BLOCK) void k_median(Launch L)
 {
     int e, local;
     if (!block_entry(L, e, local)) return;
     const IoArgs &A = const_view<JobArgs>(L.table, const_view<Entry>(L.entries, e)->job)->io;
-    const long long i = (long long)local * BLOCK + threadIdx.x;
-    if (i >= (long long)A.W * A.H) return;
-    median_one(A, i);
+    const int tiles_x = (A.W + MED_TW - 1) / MED_TW;
+    const int ty = local / tiles_x, tx = local - ty * tiles_x;
+    const int x0 = tx * MED_TW, y0 = ty * MED_TH;
+    const int x = x0 + (int)(threadIdx.x % MED_TW), y = y0 + (int)(threadIdx.x / MED_TW);
+    const bool pixel = x < A.W && y < A.H;
+    const int R = A.median_radius;
+    if (R > 2) {
+        if (!pixel) return;
+        const float d = state_depth(A, x, y);
+        if (d > 0.0f) median_wide(A, x, y, d);
+        return;
+    }
+    constexpr int SW = MED_TW + 4, SH = MED_TH + 4;
+    __shared__ float tile[SH][SW];
+    for (int c = threadIdx.x; c < SW * SH; c += BLOCK) {
+        const int r = c / SW, col = c - r * SW;
+        const int yy = y0 - 2 + r;
+        const int xx = ((x0 - 2 + col) % A.W + A.W) % A.W;
+        tile[r][col] = yy >= 0 && yy < A.H ? state_depth(A, xx, yy) : 0.0f;
+    }
+    __syncthreads();
+    if (!pixel) return;
+    const int lx = x - x0 + 2, ly = y - y0 + 2;
+    const float d = tile[ly][lx];
+    if (!(d > 0.0f)) return;
+    float v[25];
+    int n = 0;
+#pragma unroll
+    for (int dy = -2; dy <= 2; ++dy)
+#pragma unroll
+        for (int dx = -2; dx <= 2; ++dx) {
+            const float vv = abs(dy) <= R && abs(dx) <= R ? tile[ly + dy][lx + dx] : 0.0f;
+            v[(dy + 2) * 5 + dx + 2] = vv;
+            n += vv > 0.0f ? 1 : 0;
+        }
+    median_reject(A, x, y, d, lower_median25(v, n));
 }
 
 // Plane state from caller planes (test hook).

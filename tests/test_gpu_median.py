@@ -67,10 +67,13 @@ def test_median_end_to_end(pms):
     assert frac >= 0.99 and same_removed >= 0.99
 
 
-@pytest.mark.parametrize("W,radius", [(24, 3), (24, 8), (6, 8)])
+@pytest.mark.parametrize("W,radius", [(24, 3), (24, 8), (6, 8), (6, 2), (24, 1), (210, 2)])
 def test_median_window_wider_than_a_tiny_image(pms, W, radius):
     """Windows of up to 17 columns on keyframes 24 and 6 pixels wide: the
-    longitude wraps, more than once on the narrow one, as in the oracle."""
+    longitude wraps, more than once on the narrow one, as in the oracle;
+    5x5 and 3x3 windows (read from workgroup-staged tiles of 64 x 4 pixels)
+    on those and on a 210 x 105 keyframe whose last tile column and row are
+    partial."""
     w = synth.scaled("box_room", W, seed=6)
     params = dict(w.params, patch_size=3, patch_stride=1, iterations=0, median_radius=radius,
                   median_rel=0.05, offsets=[(-1, 0), (1, 0), (0, -1), (0, 1)])
