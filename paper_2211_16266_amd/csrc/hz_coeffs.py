@@ -4,9 +4,10 @@ warped sample ray (pms_kernels.hpp, the short longitude form).
 For a ray (y0, y1, y2) with y2 > 0 and tau = y0 / y2, the horizontal length
 is hz = y2 sqrt(1 + tau^2) = y2 + y2 tau^2 G(tau^2), G(u) = 1 / (1 + sqrt(1
 + u)). In the short longitude form |tau| <= tan(pi/8), so u lies in
-[0, tan^2(pi/8)]; there G is approximated by a polynomial of degree 4 that
+[0, tan^2(pi/8)]; there G is approximated by a polynomial of degree 3 that
 minimises the maximum RELATIVE error (a linear program on 4001 points;
-scipy's HiGHS). hz enters the kernels only through hz - hz_c, the increment
+scipy's HiGHS): 2.8e-7, so hz itself is off by at most u G(u) 2.8e-7 of
+y2, i.e. 2.7e-8 of hz, below its float32 rounding. hz enters the kernels only through hz - hz_c, the increment
 from the anchor, formed as e2 + y2 u G(u) - K_c without cancellation.
 Run this file to print the coefficients (as float32) and the error of the
 float32 evaluation; the kernels hold the printed values.
@@ -14,7 +15,7 @@ float32 evaluation; the kernels hold the printed values.
 import numpy as np
 from scipy.optimize import linprog
 
-DEGREE = 4
+DEGREE = 3
 U_MAX = float(np.tan(np.pi / 8)) ** 2
 
 
@@ -55,5 +56,5 @@ if __name__ == "__main__":
     u = np.linspace(0.0, U_MAX, 2_000_001).astype(np.float32)
     ref = g_exact(u.astype(np.float64))
     rel = np.abs(eval_f32(c, u).astype(np.float64) - ref) / ref
-    print("coefficients (c0..c4):", ", ".join(f"{float(x):.9e}f" for x in c))
+    print(f"coefficients (c0..c{DEGREE}):", ", ".join(f"{float(x):.9e}f" for x in c))
     print(f"exact-arithmetic relative error {e:.3e}, float32 evaluation {rel.max():.3e}")

@@ -328,9 +328,10 @@ __device__ __forceinline__ int floor_int(float x)
     return r;
 }
 
-// atan(t) for |t| <= tan(pi/8): t + t s P(s), s = t^2, with a degree-3 P
-// fitted for minimum relative error (8e-8 in FP32; atan_coeffs.py). Odd in
-// t bit for bit: round-to-nearest is symmetric.
+// atan(t) for |t| <= tan(pi/8): t + t s P(s), s = t^2, with a degree-2 P
+// fitted for minimum relative error (7.1e-7 in FP32; atan_coeffs.py): a
+// sample 5 px from its anchor lands within 4e-6 px of the exact angle's
+// position. Odd in t bit for bit: round-to-nearest is symmetric.
 constexpr float TAN_PI_8 = 0.41421356f;
 // tan(pi/8) less a margin for the rounding of the range test itself
 constexpr float SHORT_RANGE = 0.4141f;
@@ -338,22 +339,22 @@ constexpr float SHORT_RANGE = 0.4141f;
 __device__ __forceinline__ float atan_core(float t)
 {
     const float s = t * t;
-    float p = fmaf(s, 8.053722978e-02f, -1.387767941e-01f);
-    p = fmaf(p, s, 1.997770965e-01f);
-    p = fmaf(p, s, -3.333294988e-01f);
+    float p = fmaf(s, -1.122516319e-01f, 1.971414387e-01f);
+    p = fmaf(p, s, -3.332550824e-01f);
     return fmaf(t * s, p, t);
 }
 
 // G(u) = 1 / (1 + sqrt(1 + u)) for u in [0, tan^2(pi/8)], so that
-// y2 sqrt(1 + tau^2) = y2 + y2 u G(u) with u = tau^2: degree 4, fitted for
-// minimum relative error (8e-9 in exact arithmetic, 5e-8 evaluated in FP32;
-// hz_coeffs.py).
+// y2 sqrt(1 + tau^2) = y2 + y2 u G(u) with u = tau^2: degree 3, fitted for
+// minimum relative error (2.8e-7 in exact arithmetic, 3.3e-7 evaluated in
+// FP32; hz_coeffs.py). The error enters the length through y2 u G(u) only,
+// so the length itself is off by at most 2.7e-8 of it, below its FP32
+// rounding.
 __device__ __forceinline__ float hz_core(float u)
 {
-    float p = fmaf(u, 2.019176260e-02f, -3.806483746e-02f);
-    p = fmaf(p, u, 6.244114041e-02f);
-    p = fmaf(p, u, -1.249987707e-01f);
-    return fmaf(p, u, 0.5f);
+    float p = fmaf(u, -3.114441782e-02f, 6.170029193e-02f);
+    p = fmaf(p, u, -1.249734089e-01f);
+    return fmaf(p, u, 4.999998510e-01f);
 }
 
 // atan2 for any arguments (both zero give 0): octant reduction to t in
@@ -675,7 +676,7 @@ __device__ __forceinline__ float warp_samples(const SweepArgs &A, const Patch<SP
 {
     const float y0c = V.y0c, y2c = V.y2c, kc = V.kc, sdc = V.sdc, cdc = V.cdc;
     const float sp0 = V.sp0, cp0 = V.cp0;
-    float sum = 0.0f;
+    float sum;
     typename CellBits<PT>::type q[SPL];
     float fu[SPL], fv[SPL];
 #pragma unroll
@@ -729,7 +730,9 @@ __device__ __forceinline__ float warp_samples(const SweepArgs &A, const Patch<SP
 #pragma unroll
     for (int i = 0; i < SPL; ++i) {
         s[i] = blend_cell<PT>(q[i], fu[i], fv[i]);
-        sum += FULL ? s[i] : s[i] * pt.wt[i];
+        const float si = FULL ? s[i] : s[i] * pt.wt[i];
+        // (the first term starts the sum: 0 + x costs an addition)
+        sum = i == 0 ? si : sum + si;
     }
     return sum;
 }
