@@ -372,9 +372,10 @@ NEXT_BYTES = {
     "warp": 60,
     # the plane state read once (16); the window re-reads hit the caches
     "median": 16,
-    # 2 table slots of 16 cleared, depth read twice 8, CAS 8 + atomic min 8,
-    # key and order read back 16, keep byte 1
-    "fuse": 73,
+    # table slots of 16 cleared (2^24 for 9.2 M points: 29 per point), depth
+    # 4, the slot read by the insertion 16, claimed-slot index written and
+    # read 8, keep byte 1 (the claiming points' CAS and atomic min on top)
+    "fuse": 58,
     # depth 4, keep byte 1, cover byte 1
     "coverage": 6,
     # one FP64 point 24

@@ -367,9 +367,10 @@ pms_status pms_view_filter(pms_context *ctx, const double centre_a[3], const dou
    from the first map's camera centre along an axis are not kept (with
    depths up to depth_max around nearby cameras this needs voxel <
    depth_max / 2^20, i.e. 0.05 mm at 50 m); world coordinates themselves may
-   be anywhere. Uses 16 bytes of context
-   scratch per slot of a hash table of at least 2 n_maps W H slots. The
-   result does not depend on scheduling. */
+   be anywhere. Uses context scratch: a hash table of 16-byte slots, the
+   power of two at or above 5/4 n_maps W H, and 4 bytes per point; a table
+   above 2^31 slots is rejected (PMS_ERR_INVALID_ARG). The result does not
+   depend on scheduling. */
 pms_status pms_fuse(pms_context *ctx, int32_t width, int32_t height, int32_t n_maps,
                     const pms_plane *depths, const pms_pose *poses, double voxel,
                     uint8_t *keep_out, uint64_t *n_kept_out, void *stream);

@@ -1845,8 +1845,14 @@ pms_status pms_fuse(pms_context *ctx, int32_t width, int32_t height, int32_t n_m
     if (st != PMS_OK) return st;
     const long long points = (long long)width * height * n_maps;
     unsigned long long cap = 1024;
-    while (cap < 2ULL * (unsigned long long)points) cap <<= 1;
-    if ((st = ensure_work(ctx, (size_t)cap * 2 * sizeof(unsigned long long), static_cast<hipStream_t>(stream))) !=
+    // load at most 0.8 if every point had a voxel of its own; a window's
+    // maps share most voxels, so the usual load is far lower
+    while (cap < (unsigned long long)points + (unsigned long long)points / 4) cap <<= 1;
+    // (32-bit slot indices, all below the NO_CLAIM marker)
+    if (cap > (1ULL << 31)) return fail(ctx, PMS_ERR_INVALID_ARG, "too many points for one fusion call");
+    // the table, then one claimed-slot index per point
+    const size_t table_bytes = (size_t)cap * 2 * sizeof(unsigned long long);
+    if ((st = ensure_work(ctx, table_bytes + (size_t)points * sizeof(unsigned), static_cast<hipStream_t>(stream))) !=
         PMS_OK)
         return st;
     A.voxel = voxel;
@@ -1862,13 +1868,21 @@ pms_status pms_fuse(pms_context *ctx, int32_t width, int32_t height, int32_t n_m
     }
     A.slots = static_cast<unsigned long long *>(ctx->work);
     A.mask = cap - 1;
+    A.claim = reinterpret_cast<unsigned *>(static_cast<char *>(ctx->work) + table_bytes);
     A.keep = keep_out;
     A.count = reinterpret_cast<unsigned long long *>(n_kept_out);
     hipStream_t s = static_cast<hipStream_t>(stream);
     {
         LaunchTimer timer(ctx, KK_FUSE, s);
         hipLaunchKernelGGL(pms::k_fuse_clear, dim3((unsigned)blocks_of((long long)cap)), dim3(pms::BLOCK), 0, s, A);
-        hipLaunchKernelGGL(pms::k_fuse_insert, dim3((unsigned)blocks_of(points)), dim3(pms::BLOCK), 0, s, A);
+        // one launch per map, in map order; one wave per FUSE_TILE x
+        // FUSE_TILE tile
+        const long long tiles = (long long)((width + pms::FUSE_TILE - 1) / pms::FUSE_TILE) *
+                                ((height + pms::FUSE_TILE - 1) / pms::FUSE_TILE);
+        for (int m = 0; m < n_maps; ++m)
+            hipLaunchKernelGGL(pms::k_fuse_insert,
+                               dim3((unsigned)((tiles + pms::BLOCK / 64 - 1) / (pms::BLOCK / 64))), dim3(pms::BLOCK),
+                               0, s, A, m);
         hipLaunchKernelGGL(pms::k_fuse_mark, dim3(count_grid(points)), dim3(pms::BLOCK), 0, s, A);
     }
     hipError_t e = hipGetLastError();

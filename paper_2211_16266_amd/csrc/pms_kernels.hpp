@@ -1917,7 +1917,8 @@ struct FuseArgs {
     // hash table of 16-byte slots: voxel key at [2h], first (map, pixel) at
     // [2h + 1], so that a point's claim and order share one cache line
     unsigned long long *slots;
-    unsigned long long mask;          // capacity - 1 (a power of two)
+    unsigned long long mask;          // capacity - 1 (a power of two, <= 2^31)
+    unsigned *claim;                  // per point: its voxel's slot, or NO_CLAIM
     unsigned char *keep;              // n_maps x H x W
     unsigned long long *count;
     // coverage
@@ -1978,60 +1979,86 @@ __global__ __launch_bounds__(BLOCK) void k_fuse_clear(FuseArgs A)
 }
 
 // Each point claims its voxel's slot (linear probing; the table holds at
-// least twice as many slots as points, so a free slot is always found) and
-// lowers the slot's value to its (map, pixel) order. Neighbouring pixels
-// often fall into one voxel: a point whose left neighbour in the wave (the
-// order just below its own) has the same voxel leaves the claim to it, as
-// the first point of such a run carries the lowest order; this removes
-// contended atomics without changing any slot's final value.
-__global__ __launch_bounds__(BLOCK) void k_fuse_insert(FuseArgs A)
+// least 5/4 as many slots as points, so a free slot is always found) and
+// lowers the slot's value to its (map, pixel) order. A slot's key, once
+// written, never changes: a plain read that shows a key is final, and only
+// a slot that reads as empty (possibly a stale copy) needs the CAS.
+//
+// One launch per map, in map order. A slot whose order already names an
+// earlier map (written by an earlier launch, so final) keeps that order,
+// which every point of this map exceeds: such points only read.
+//
+// A wave takes an 8 x 8 pixel tile of the map. Neighbouring pixels often
+// fall into one voxel: a point whose left or upper neighbour in the tile
+// (both of lower order) has the same voxel leaves the claim to it. Every
+// skipped point has a lower-order point of its voxel in the wave, and the
+// lowest-order one of the wave never skips, so each slot still ends with
+// its voxel's lowest order, with fewer contended atomics. Every point of
+// the map records the slot it claimed, or NO_CLAIM (no valid voxel, or a
+// lower-order point of its voxel exists: such a point is never the first
+// of its voxel).
+constexpr int FUSE_TILE = 8;
+constexpr unsigned NO_CLAIM = 0xffffffffu;
+
+__global__ __launch_bounds__(BLOCK) void k_fuse_insert(FuseArgs A, int m)
 {
-    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = (int)(threadIdx.x & 63u);
+    const int wave = (int)(blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6));
+    const int tiles_x = (A.W + FUSE_TILE - 1) / FUSE_TILE;
+    const int ty = wave / tiles_x, tx = wave - ty * tiles_x;
+    const int x = tx * FUSE_TILE + lane % FUSE_TILE, y = ty * FUSE_TILE + lane / FUSE_TILE;
     const long long HW = (long long)A.W * A.H;
+    const long long g = (long long)m * HW + (long long)y * A.W + x;
+    const bool in_range = x < A.W && y < A.H;
     unsigned long long key = 0ULL;
     bool have = false;
-    if (g < HW * A.n_maps) {
-        const int m = (int)(g / HW);
+    if (in_range) {
         double X[3];
-        have = fuse_point(A, m, g - (long long)m * HW, X) && voxel_key(A, X, key);
+        have = fuse_point(A, m, (long long)y * A.W + x, X) && voxel_key(A, X, key);
     }
     const unsigned lo = (unsigned)key, hi = (unsigned)(key >> 32);
-    const unsigned left_lo = __shfl_up(lo, 1, 64), left_hi = __shfl_up(hi, 1, 64);
-    const int left_have = __shfl_up(have ? 1 : 0, 1, 64);
-    const bool run = (threadIdx.x & 63) != 0 && left_have && left_lo == lo && left_hi == hi;
-    if (!have || run) return;
+    const int hv = have ? 1 : 0;
+    const unsigned l_lo = __shfl_up(lo, 1, 64), l_hi = __shfl_up(hi, 1, 64);
+    const int l_have = __shfl_up(hv, 1, 64);
+    const unsigned u_lo = __shfl_up(lo, FUSE_TILE, 64), u_hi = __shfl_up(hi, FUSE_TILE, 64);
+    const int u_have = __shfl_up(hv, FUSE_TILE, 64);
+    const bool left = lane % FUSE_TILE != 0 && l_have && l_lo == lo && l_hi == hi;
+    const bool up = lane >= FUSE_TILE && u_have && u_lo == lo && u_hi == hi;
+    if (!have || left || up) {
+        if (in_range) A.claim[g] = NO_CLAIM;
+        return;
+    }
+    const unsigned long long first = (unsigned long long)m * (unsigned long long)HW;
     unsigned long long h = hash64(key) & A.mask;
     for (unsigned long long probe = 0; probe <= A.mask; ++probe) {
-        const unsigned long long prev = atomicCAS(&A.slots[2 * h], EMPTY_KEY, key);
+        // key and order in one 16-byte read
+        const ulonglong2 sl = *reinterpret_cast<const ulonglong2 *>(&A.slots[2 * h]);
+        if (sl.x == key && sl.y < first) {
+            A.claim[g] = NO_CLAIM;
+            return;
+        }
+        unsigned long long prev = sl.x;
+        if (prev == EMPTY_KEY) prev = atomicCAS(&A.slots[2 * h], EMPTY_KEY, key);
         if (prev == EMPTY_KEY || prev == key) {
             atomicMin(&A.slots[2 * h + 1], (unsigned long long)g);
+            A.claim[g] = (unsigned)h;
             return;
         }
         h = (h + 1) & A.mask;
     }
+    // (not reached: the table always has a free slot)
+    A.claim[g] = NO_CLAIM;
 }
 
-// keep = this point is the first of its voxel; the workgroup adds its count.
+// keep = this point is the first of its voxel: it claimed a slot and the
+// slot's lowest order is its own. The workgroup adds its count.
 __global__ __launch_bounds__(BLOCK) void k_fuse_mark(FuseArgs A)
 {
     const long long HW = (long long)A.W * A.H, n = HW * A.n_maps;
     unsigned n_kept = 0;
     for (long long g = (long long)blockIdx.x * BLOCK + threadIdx.x; g < n; g += (long long)gridDim.x * BLOCK) {
-        bool kept = false;
-        const int m = (int)(g / HW);
-        double X[3];
-        unsigned long long key;
-        if (fuse_point(A, m, g - (long long)m * HW, X) && voxel_key(A, X, key)) {
-            unsigned long long h = hash64(key) & A.mask;
-            for (unsigned long long probe = 0; probe <= A.mask; ++probe) {
-                if (A.slots[2 * h] == key) {
-                    kept = A.slots[2 * h + 1] == (unsigned long long)g;
-                    break;
-                }
-                if (A.slots[2 * h] == EMPTY_KEY) break;
-                h = (h + 1) & A.mask;
-            }
-        }
+        const unsigned h = A.claim[g];
+        const bool kept = h != NO_CLAIM && A.slots[2 * (unsigned long long)h + 1] == (unsigned long long)g;
         A.keep[g] = kept ? 1 : 0;
         n_kept += kept ? 1 : 0;
     }

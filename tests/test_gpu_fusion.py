@@ -28,10 +28,15 @@ def _maps(W):
     return w, [w.gt_depth[k].astype(np.float32) for k in ks], [w.poses[k] for k in ks]
 
 
-@pytest.mark.parametrize("W,voxel", [(384, 0.02), (384, 0.1), (384, 0.5), (1920, 0.02)])
-def test_keep_masks_match_oracle(pms, W, voxel):
+@pytest.mark.parametrize("W,voxel,n_maps", [(384, 0.02, 4), (384, 0.1, 4), (384, 0.5, 4), (1920, 0.02, 4),
+                                            (210, 0.03, 4), (102, 0.05, 1), (102, 0.01, 3)])
+def test_keep_masks_match_oracle(pms, W, voxel, n_maps):
+    """Also on sizes whose 8 x 8 insertion tiles are partial at the right and
+    bottom (210 x 105, 102 x 51) and with one and three maps (the insertion
+    runs one launch per map)."""
     w, depths, poses = _maps(W)
-    say(f"fuse 4 maps {W}x{W // 2} voxel {voxel}")
+    depths, poses = depths[:n_maps], poses[:n_maps]
+    say(f"fuse {n_maps} maps {W}x{W // 2} voxel {voxel}")
     keep_g, n_g = pms.fuse([torch.from_numpy(d).cuda() for d in depths], poses, voxel)
     torch.cuda.synchronize()
     keep_o, n_o = oracle.fuse([d.astype(np.float64) for d in depths], poses, voxel)
