@@ -351,7 +351,7 @@ pms_status pms_warp_planes(pms_context *ctx, int32_t width, int32_t height,
    (counts_out[0]) and those not at a centre (counts_out[1]); counts_out is
    two uint64 in device memory, overwritten. The keyframe is accepted when
    counts_out[0] >= 0.2 counts_out[1] (the paper's 20%, 6 and 60 degrees).
-   Angles in FP64. */
+   Angles in FP64. Uses 16 KB of context scratch (spread counters). */
 pms_status pms_view_filter(pms_context *ctx, const double centre_a[3], const double centre_b[3],
                            const double *points, int64_t n_points, double min_deg,
                            double max_deg, uint64_t *counts_out, void *stream);
@@ -368,7 +368,8 @@ pms_status pms_view_filter(pms_context *ctx, const double centre_a[3], const dou
    depths up to depth_max around nearby cameras this needs voxel <
    depth_max / 2^20, i.e. 0.05 mm at 50 m); world coordinates themselves may
    be anywhere. Uses context scratch: a hash table of 16-byte slots, the
-   power of two at or above 5/4 n_maps W H, and 4 bytes per point; a table
+   power of two at or above 5/4 n_maps W H, 4 bytes per point and 16 KB of
+   spread counters; a table
    above 2^31 slots is rejected (PMS_ERR_INVALID_ARG). The result does not
    depend on scheduling. */
 pms_status pms_fuse(pms_context *ctx, int32_t width, int32_t height, int32_t n_maps,
@@ -381,7 +382,8 @@ pms_status pms_fuse(pms_context *ctx, int32_t width, int32_t height, int32_t n_m
    pixel of an out_width x out_height equirectangular image at view_pose
    nearest to its projection. Writes cover_out (device, out_width *
    out_height bytes, 1 = marked) and the number of marked pixels to
-   n_covered_out (device uint64). */
+   n_covered_out (device uint64). Uses 16 KB of context scratch (spread
+   counters). */
 pms_status pms_coverage(pms_context *ctx, int32_t width, int32_t height, int32_t n_maps,
                         const pms_plane *depths, const pms_pose *poses, const uint8_t *keep,
                         const pms_pose *view_pose, int32_t out_width, int32_t out_height,

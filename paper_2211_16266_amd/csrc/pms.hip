@@ -1780,17 +1780,22 @@ pms_status pms_view_filter(pms_context *ctx, const double centre_a[3], const dou
     if (st != PMS_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     unsigned long long *counts = reinterpret_cast<unsigned long long *>(counts_out);
+    // the spread counters in the context's block
+    if ((st = ensure_work(ctx, pms::COUNT_SPREAD_BYTES, s)) != PMS_OK) return st;
+    unsigned long long *spread = static_cast<unsigned long long *>(ctx->work);
     {
         LaunchTimer timer(ctx, KK_VIEW, s);
-        hipLaunchKernelGGL(pms::k_count_clear, dim3(1), dim3(64), 0, s, counts);
+        hipLaunchKernelGGL(pms::k_count_clear, dim3(1), dim3(2 * pms::COUNT_SPREAD), 0, s, spread);
         if (n_points > 0)
             hipLaunchKernelGGL(pms::k_view_filter, dim3(count_grid(n_points)), dim3(pms::BLOCK), 0,
                                s, centre_a[0], centre_a[1], centre_a[2], centre_b[0], centre_b[1],
-                               centre_b[2], points, (long long)n_points, min_deg, max_deg, counts);
+                               centre_b[2], points, (long long)n_points, min_deg, max_deg, spread);
+        hipLaunchKernelGGL(pms::k_count_gather, dim3(1), dim3(pms::COUNT_SPREAD), 0, s, spread, counts,
+                           counts + 1);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(ctx, e, "view filter");
-    return PMS_OK;
+    return mark_work_used(ctx, s);
 }
 
 }  // extern "C"
@@ -1850,10 +1855,10 @@ pms_status pms_fuse(pms_context *ctx, int32_t width, int32_t height, int32_t n_m
     while (cap < (unsigned long long)points + (unsigned long long)points / 4) cap <<= 1;
     // (32-bit slot indices, all below the NO_CLAIM marker)
     if (cap > (1ULL << 31)) return fail(ctx, PMS_ERR_INVALID_ARG, "too many points for one fusion call");
-    // the table, then one claimed-slot index per point
+    // the table, one claimed-slot index per point, then the spread counters
     const size_t table_bytes = (size_t)cap * 2 * sizeof(unsigned long long);
-    if ((st = ensure_work(ctx, table_bytes + (size_t)points * sizeof(unsigned), static_cast<hipStream_t>(stream))) !=
-        PMS_OK)
+    const size_t spread_off = (table_bytes + (size_t)points * sizeof(unsigned) + 255) & ~(size_t)255;
+    if ((st = ensure_work(ctx, spread_off + pms::COUNT_SPREAD_BYTES, static_cast<hipStream_t>(stream))) != PMS_OK)
         return st;
     A.voxel = voxel;
     {
@@ -1869,6 +1874,7 @@ pms_status pms_fuse(pms_context *ctx, int32_t width, int32_t height, int32_t n_m
     A.slots = static_cast<unsigned long long *>(ctx->work);
     A.mask = cap - 1;
     A.claim = reinterpret_cast<unsigned *>(static_cast<char *>(ctx->work) + table_bytes);
+    A.spread = reinterpret_cast<unsigned long long *>(static_cast<char *>(ctx->work) + spread_off);
     A.keep = keep_out;
     A.count = reinterpret_cast<unsigned long long *>(n_kept_out);
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1884,6 +1890,8 @@ pms_status pms_fuse(pms_context *ctx, int32_t width, int32_t height, int32_t n_m
                                dim3((unsigned)((tiles + pms::BLOCK / 64 - 1) / (pms::BLOCK / 64))), dim3(pms::BLOCK),
                                0, s, A, m);
         hipLaunchKernelGGL(pms::k_fuse_mark, dim3(count_grid(points)), dim3(pms::BLOCK), 0, s, A);
+        hipLaunchKernelGGL(pms::k_count_gather, dim3(1), dim3(pms::COUNT_SPREAD), 0, s, A.spread, A.count,
+                           (unsigned long long *)nullptr);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(ctx, e, "fuse");
@@ -1914,15 +1922,23 @@ pms_status pms_coverage(pms_context *ctx, int32_t width, int32_t height, int32_t
     const long long points = (long long)width * height * n_maps;
     const long long pix = (long long)out_width * out_height;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    // the spread counters in the context's block
+    if ((st = ensure_work(ctx, pms::COUNT_SPREAD_BYTES, s)) != PMS_OK) return st;
+    A.spread = static_cast<unsigned long long *>(ctx->work);
     {
         LaunchTimer timer(ctx, KK_COVER, s);
         hipLaunchKernelGGL(pms::k_cover_clear, dim3((unsigned)blocks_of(pix)), dim3(pms::BLOCK), 0, s, A);
-        hipLaunchKernelGGL(pms::k_cover_mark, dim3((unsigned)blocks_of(points)), dim3(pms::BLOCK), 0, s, A);
+        // one wave per COVER_SPAN points
+        const long long waves = (points + pms::COVER_SPAN - 1) / pms::COVER_SPAN;
+        hipLaunchKernelGGL(pms::k_cover_mark, dim3((unsigned)((waves + pms::BLOCK / 64 - 1) / (pms::BLOCK / 64))),
+                           dim3(pms::BLOCK), 0, s, A);
         hipLaunchKernelGGL(pms::k_cover_count, dim3(count_grid(pix)), dim3(pms::BLOCK), 0, s, A);
+        hipLaunchKernelGGL(pms::k_count_gather, dim3(1), dim3(pms::COUNT_SPREAD), 0, s, A.spread, A.count,
+                           (unsigned long long *)nullptr);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(ctx, e, "coverage");
-    return PMS_OK;
+    return mark_work_used(ctx, s);
 }
 
 pms_status pms_philox_stream(pms_context *ctx, uint64_t key0, uint64_t key1, uint64_t ctr0,

@@ -1835,21 +1835,55 @@ __global__ __launch_bounds__(BLOCK) void k_warp_resolve(WarpArgs A)
 // view filter (Sec. III-A, Eq. 1)
 // ---------------------------------------------------------------------------
 
-__global__ void k_count_clear(unsigned long long *counts)
+// Counters of the counting kernels (view filter, fuse marks, coverage),
+// spread over COUNT_SPREAD slots a cache line apart per counter: workgroup
+// w adds its sums to slot w % COUNT_SPREAD with one atomic each, so the
+// atomics of different slots proceed in parallel instead of serialising on
+// one address (at one address, ~13 ns each: 2048 of them were most of a
+// 29 us view filter), and k_count_gather adds the slots up.
+constexpr int COUNT_SPREAD = 64;
+static_assert(BLOCK >= 2 * COUNT_SPREAD, "a clearing workgroup covers every slot");
+constexpr int COUNT_PAD = 16;  // unsigned long longs per slot (128 bytes)
+constexpr size_t COUNT_SPREAD_BYTES = 2 * COUNT_SPREAD * COUNT_PAD * sizeof(unsigned long long);
+
+__device__ __forceinline__ unsigned long long *count_slot(unsigned long long *spread, int counter, int slot)
 {
-    if (threadIdx.x < 2) counts[threadIdx.x] = 0ULL;
+    return spread + ((size_t)counter * COUNT_SPREAD + slot) * COUNT_PAD;
+}
+
+// Zeroes both counters' slots (one workgroup of 2 * COUNT_SPREAD threads).
+__global__ void k_count_clear(unsigned long long *spread)
+{
+    if (threadIdx.x < 2 * COUNT_SPREAD)
+        *count_slot(spread, (int)threadIdx.x / COUNT_SPREAD, (int)threadIdx.x % COUNT_SPREAD) = 0ULL;
+}
+
+// out0 (and out1, unless null) = the sums of the two counters' slots (one
+// wave of COUNT_SPREAD threads).
+__global__ void k_count_gather(unsigned long long *spread, unsigned long long *out0, unsigned long long *out1)
+{
+    static_assert(COUNT_SPREAD == 64, "one slot per lane of a wave");
+    unsigned long long c0 = *count_slot(spread, 0, (int)threadIdx.x);
+    unsigned long long c1 = *count_slot(spread, 1, (int)threadIdx.x);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        c0 += __shfl_xor(c0, o, 64);
+        c1 += __shfl_xor(c1, o, 64);
+    }
+    if (threadIdx.x == 0) {
+        *out0 = c0;
+        if (out1) *out1 = c1;
+    }
 }
 
 // Workgroups of the counting kernels, which walk their items with a grid
-// stride: one counter atomic per workgroup instead of one per wave (every
-// wave's atomic on the same address serialises; at one per wave they took
-// most of these kernels' time).
-constexpr int COUNT_GRID = 1024;
+// stride.
+constexpr int COUNT_GRID = 8192;
 
-// Adds the workgroup's sums of c0 and c1 to *d0 and *d1 (d1 may be null)
-// with one atomic each; every thread of the workgroup must call it.
-__device__ __forceinline__ void block_count_add(unsigned long long *d0, unsigned c0,
-                                                unsigned long long *d1, unsigned c1)
+// Adds the workgroup's sums of c0 and c1 to slot blockIdx.x % COUNT_SPREAD
+// of the two spread counters with one atomic each; every thread of the
+// workgroup must call it.
+__device__ __forceinline__ void block_count_add(unsigned long long *spread, unsigned c0, unsigned c1)
 {
     __shared__ unsigned part[2][BLOCK / 64];
 #pragma unroll
@@ -1868,8 +1902,9 @@ __device__ __forceinline__ void block_count_add(unsigned long long *d0, unsigned
             t0 += part[0][w];
             t1 += part[1][w];
         }
-        if (t0) atomicAdd(d0, t0);
-        if (d1 && t1) atomicAdd(d1, t1);
+        const int slot = (int)(blockIdx.x % COUNT_SPREAD);
+        if (t0) atomicAdd(count_slot(spread, 0, slot), t0);
+        if (t1) atomicAdd(count_slot(spread, 1, slot), t1);
     }
 }
 
@@ -1879,7 +1914,7 @@ __device__ __forceinline__ void block_count_add(unsigned long long *d0, unsigned
 __global__ __launch_bounds__(BLOCK) void k_view_filter(double ax, double ay, double az, double bx,
                                                        double by, double bz, const double *pts,
                                                        long long n, double min_deg, double max_deg,
-                                                       unsigned long long *counts)
+                                                       unsigned long long *spread)
 {
     unsigned n_range = 0, n_counted = 0;
     for (long long i = (long long)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (long long)gridDim.x * BLOCK) {
@@ -1895,7 +1930,7 @@ __global__ __launch_bounds__(BLOCK) void k_view_filter(double ax, double ay, dou
             n_range += deg >= min_deg && deg <= max_deg ? 1 : 0;
         }
     }
-    block_count_add(&counts[0], n_range, &counts[1], n_counted);
+    block_count_add(spread, n_range, n_counted);
 }
 
 // ---------------------------------------------------------------------------
@@ -1920,7 +1955,8 @@ struct FuseArgs {
     unsigned long long mask;          // capacity - 1 (a power of two, <= 2^31)
     unsigned *claim;                  // per point: its voxel's slot, or NO_CLAIM
     unsigned char *keep;              // n_maps x H x W
-    unsigned long long *count;
+    unsigned long long *count;        // the output count
+    unsigned long long *spread;       // its spread slots (k_count_gather)
     // coverage
     ViewPoseD view;
     int Wc, Hc;
@@ -1975,7 +2011,8 @@ __global__ __launch_bounds__(BLOCK) void k_fuse_clear(FuseArgs A)
         A.slots[2 * i] = EMPTY_KEY;
         A.slots[2 * i + 1] = EMPTY_KEY;
     }
-    if (i == 0) A.count[0] = 0ULL;
+    // (the grid has at least 4 workgroups: capacity >= 1024)
+    if (i < 2 * COUNT_SPREAD) *count_slot(A.spread, (int)i / COUNT_SPREAD, (int)i % COUNT_SPREAD) = 0ULL;
 }
 
 // Each point claims its voxel's slot (linear probing; the table holds at
@@ -2062,22 +2099,21 @@ __global__ __launch_bounds__(BLOCK) void k_fuse_mark(FuseArgs A)
         A.keep[g] = kept ? 1 : 0;
         n_kept += kept ? 1 : 0;
     }
-    block_count_add(A.count, n_kept, nullptr, 0);
+    block_count_add(A.spread, n_kept, 0);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_cover_clear(FuseArgs A)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < (long long)A.Wc * A.Hc) A.cover[i] = 0;
-    if (i == 0) A.count[0] = 0ULL;
+    // (the grid has at least one workgroup of BLOCK >= 2 COUNT_SPREAD threads)
+    if (i < 2 * COUNT_SPREAD) *count_slot(A.spread, (int)i / COUNT_SPREAD, (int)i % COUNT_SPREAD) = 0ULL;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_cover_mark(FuseArgs A)
+// Marks the panorama pixel of point g (a kept point of the maps).
+__device__ __forceinline__ void cover_point(const FuseArgs &A, long long g)
 {
-    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long HW = (long long)A.W * A.H;
-    if (g >= HW * A.n_maps) return;
-    if (A.keep_in && !A.keep_in[g]) return;
     const int m = (int)(g / HW);
     double X[3];
     if (!fuse_point(A, m, g - (long long)m * HW, X)) return;
@@ -2099,13 +2135,51 @@ __global__ __launch_bounds__(BLOCK) void k_cover_mark(FuseArgs A)
     A.cover[(long long)yi * A.Wc + xi] = 1;
 }
 
+// A wave takes COVER_SPAN consecutive points: it collects the indices of
+// those with their keep byte set (or depth > 0 without keep bytes) in LDS,
+// in order, and then projects them 64 at a time, so that the FP64
+// projection runs on full waves although most points are not kept.
+constexpr int COVER_SPAN = 256;
+
+__global__ __launch_bounds__(BLOCK) void k_cover_mark(FuseArgs A)
+{
+    __shared__ long long list[BLOCK / 64][COVER_SPAN];
+    const int lane = (int)(threadIdx.x & 63u), w = (int)(threadIdx.x >> 6);
+    const long long HW = (long long)A.W * A.H, n = HW * A.n_maps;
+    const long long base = ((long long)blockIdx.x * (BLOCK / 64) + w) * COVER_SPAN;
+    int total = 0;
+#pragma unroll
+    for (int c = 0; c < COVER_SPAN / 64; ++c) {
+        const long long g = base + c * 64 + lane;
+        bool f = false;
+        if (g < n) {
+            if (A.keep_in) {
+                f = A.keep_in[g] != 0;
+            } else {
+                const int m = (int)(g / HW);
+                const long long i = g - (long long)m * HW;
+                const int y = (int)(i / A.W), x = (int)(i - (long long)y * A.W);
+                f = A.depth[m][(long long)y * A.pitch[m] + x] > 0.0f;
+            }
+        }
+        const unsigned long long mask = __ballot(f);
+        // rank of this lane among the flagged lanes below it
+        const int r = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+        if (f) list[w][total + r] = g;
+        total += __popcll(mask);
+    }
+    // (a wave's LDS writes complete before its reads)
+    __builtin_amdgcn_wave_barrier();
+    for (int j = lane; j < total; j += 64) cover_point(A, list[w][j]);
+}
+
 __global__ __launch_bounds__(BLOCK) void k_cover_count(FuseArgs A)
 {
     const long long n = (long long)A.Wc * A.Hc;
     unsigned c = 0;
     for (long long i = (long long)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (long long)gridDim.x * BLOCK)
         c += A.cover[i] ? 1 : 0;
-    block_count_add(A.count, c, nullptr, 0);
+    block_count_add(A.spread, c, 0);
 }
 
 // Test hook: raw Philox blocks.

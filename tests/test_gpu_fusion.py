@@ -60,6 +60,24 @@ def test_coverage_matches_oracle(pms):
     assert n_g == n_o and np.array_equal(cover_g.cpu().numpy(), cover_o)
 
 
+def test_coverage_of_every_point_matches_oracle(pms):
+    """Coverage without keep bytes (every point with depth > 0), three maps
+    of 208 x 104: the marking waves' last span is partial. (Seen from a map's
+    own camera, its pixel centres land exactly on panorama pixel borders
+    unless 8 divides the map height: 720 (x + 1/2) / W, 360 (y + 1/2) / H
+    is then never an integer, so no point sits on a rounding tie.)"""
+    w, depths, poses = _maps(208)
+    depths, poses = depths[:3], poses[:3]
+    depths[1][40:60, 20:90] = 0.0  # a hole: points without depth are skipped
+    dev = [torch.from_numpy(d).cuda() for d in depths]
+    say("coverage 720x360 of every point, 3 maps 208x104")
+    n_g, cover_g = pms.coverage(dev, poses, None, poses[1])
+    torch.cuda.synchronize()
+    n_o, cover_o = oracle.coverage([d.astype(np.float64) for d in depths], poses, None, poses[1])
+    print(f"covered {n_o} pixels")
+    assert n_o > 0 and n_g == n_o and np.array_equal(cover_g.cpu().numpy(), cover_o)
+
+
 def _shifted(poses, offset):
     """The same cameras in a world frame moved by `offset` (metres)."""
     o = np.asarray(offset, dtype=np.float64)
