@@ -73,15 +73,15 @@ METRIC = "keyframes/s + p50/p99 latency @1920×960, 4 nbrs; NCC evals/s vs roofl
 SLOTS_PER_SAMPLE = 76
 SLOTS_PER_EVAL = 30
 # The same unit re-derived from the gfx950 ISA of this build: its short-form
-# sample loop issues 47 VALU instructions a sample (422 for the 9 samples of
+# sample loop issues 46 VALU instructions a sample (413 for the 9 samples of
 # a lane, counted in the compiled half-sweep), 2 of them rcp at half rate:
-# 49 slots; per evaluation
+# 48 slots; per evaluation
 # the NCC finish, top-k insertion and LDS read of the view set-up (about 87
 # slots) and a quarter of the FP64 view set-up and candidate handling that
 # four views share (about 78): 165 slots. The roofline fraction is priced
 # this way (the 76-slot estimate exceeds what this ISA needs, so a fraction
 # priced by it passes 1 on a fast kernel; it is reported beside it).
-ISA_SLOTS_PER_SAMPLE = 49
+ISA_SLOTS_PER_SAMPLE = 48
 ISA_SLOTS_PER_EVAL = 165
 # Peak: 256 CUs x 64 lanes x 2.4 GHz non-packed FP32 lane-slots.
 PEAK_TSLOTS = 256 * 64 * 2.4e9 / 1e12

@@ -711,12 +711,15 @@ __device__ __forceinline__ float warp_samples(const SweepArgs &A, const Patch<SP
         const float au = __builtin_amdgcn_fractf(ul), av = __builtin_amdgcn_fractf(vl);
         // |ul| <= W/2 keeps the column inside the repeated storage and the
         // latitude stays within the poles, so the cell lies inside the
-        // storage; the clamp only keeps every address there whatever the
-        // inputs
-        const int off = clamp0_int(
-            (int)(((unsigned)(__mul24(floor_int(vl), A.Wp) + floor_int(ul)) << cell_shift<PT>()) +
-                  (unsigned)V.base),
-            last);
+        // storage. Whatever the inputs, no load leaves it: an offset past
+        // the end (a negative one wraps to a large unsigned value) fails the
+        // buffer descriptor's range check and reads zeros. The clamp into
+        // the storage is kept where it is free, in the ragged variants (13
+        // samples: 7% faster with it, register allocation), and left out of
+        // the full ones (1-2% faster without).
+        int off = (int)(((unsigned)(__mul24(floor_int(vl), A.Wp) + floor_int(ul)) << cell_shift<PT>()) +
+                        (unsigned)V.base);
+        if (!FULL) off = clamp0_int(off, last);
         q[i] = load_cell<PT>(img, off);
         fu[i] = au;
         fv[i] = av;
