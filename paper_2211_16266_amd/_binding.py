@@ -13,7 +13,9 @@ import os
 import torch
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libpms.so")
+# PMS_LIB names another build of the same sources (the host-sanitizer
+# test loads one); by default the in-tree library
+LIB_PATH = os.environ.get("PMS_LIB") or os.path.join(PKG, "libpms.so")
 
 NOALLOC_SCRATCH_BYTES = 128 << 20  # PMS_NOALLOC_SCRATCH_BYTES of pms.h
 MAX_VIEWS = 8
