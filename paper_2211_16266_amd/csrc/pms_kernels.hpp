@@ -2071,7 +2071,11 @@ __global__ __launch_bounds__(BLOCK) void k_fuse_insert(FuseArgs A, int m)
     const unsigned long long first = (unsigned long long)m * (unsigned long long)HW;
     unsigned long long h = hash64(key) & A.mask;
     for (unsigned long long probe = 0; probe <= A.mask; ++probe) {
-        // key and order in one 16-byte read
+        // key and order in one 16-byte read. It may race with this launch's
+        // atomics and see either half stale; a stale key reads as empty
+        // and an order of this map is not below `first`, so such a read
+        // only sends the point on to the CAS and the atomic min, which are
+        // exact. Only what earlier launches wrote can skip them.
         const ulonglong2 sl = *reinterpret_cast<const ulonglong2 *>(&A.slots[2 * h]);
         if (sl.x == key && sl.y < first) {
             A.claim[g] = NO_CLAIM;
