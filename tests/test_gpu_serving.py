@@ -2,7 +2,8 @@
 
 * Requests that arrive while others are on the GPU are admitted as memory
   frees up, share launches with them, and every result equals that of
-  pms_densify on the same job alone, bit for bit.
+  pms_densify on the same job alone, bit for bit (some of them with the
+  median post-filter, which the server plans per job).
 * Admission respects the arena: with room for about two jobs, no more run
   at once, all finish, and a job larger than the arena is refused at
   submission with PMS_ERR_BUDGET.
@@ -33,9 +34,9 @@ def _tensors(pool):
     return {W: [torch.from_numpy(a).cuda() for a in w.images] for W, w in pool.items()}
 
 
-def _jobdesc(pms, pool, dev, mj, iterations):
+def _jobdesc(pms, pool, dev, mj, iterations, median_radius=0):
     w = pool[mj.W]
-    params = dict(w.params, iterations=iterations, seed=mj.seed)
+    params = dict(w.params, iterations=iterations, seed=mj.seed, median_radius=median_radius)
     imgs = dev[mj.W]
     return pms.job(imgs[mj.ref], [imgs[k] for k in mj.nbrs], w.poses[mj.ref],
                    [w.poses[k] for k in mj.nbrs], params)
@@ -47,8 +48,10 @@ def test_served_results_equal_solo_runs(pms, pool):
     ctx = pms.Context(0)
     reqs = synth.poisson_requests(3, 4.0, 3.0, seed=11, widths=(128, 192, 256))[:12]
     assert len(reqs) == 12
-    # bursts of four, 20 ms apart: later bursts join jobs still in flight
-    requests = [serving.Request(0.02 * (k // 4), _jobdesc(pms, pool, dev, mj, 2 + (k % 2)), tag=k)
+    # bursts of four, 20 ms apart: later bursts join jobs still in flight;
+    # every third job with the 5x5 median post-filter
+    requests = [serving.Request(0.02 * (k // 4), _jobdesc(pms, pool, dev, mj, 2 + (k % 2), 2 if k % 3 == 0 else 0),
+                                tag=k)
                 for k, (t, s, mj) in enumerate(reqs)]
     server = pms.Server(arena_bytes=64 << 20, max_jobs=8, ctx=ctx)
     say(f"serving {len(requests)} requests")
