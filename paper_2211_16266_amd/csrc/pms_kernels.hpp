@@ -1761,6 +1761,53 @@ __device__ __forceinline__ void warp_point(const WarpArgs &A, int x, int y, floa
     for (int k = 0; k < 3; ++k) Y[k] = A.R[3 * k] * X0 + A.R[3 * k + 1] * X1 + A.R[3 * k + 2] * X2 + A.t[k];
 }
 
+// Nearest pixel of a Wc x Hc equirectangular image to direction Y, in FP64:
+// u = Wc (atan2(Y0, Y2) + pi) / (2 pi) - 0.5, v = Hc (pi/2 - atan2(-Y1,
+// |(Y0, Y2)|)) / pi - 0.5, the column floor(u + 1/2) wrapped, the row
+// floor(v + 1/2) clamped.
+__device__ __forceinline__ void nearest_pixel64(const double Y[3], int Wc, int Hc, int &xi, int &yi)
+{
+    const double PI = 3.14159265358979323846;
+    const double lam = atan2(Y[0], Y[2]);
+    const double phi = atan2(-Y[1], hypot(Y[0], Y[2]));
+    const double u = Wc * (lam + PI) / (2.0 * PI) - 0.5;
+    const double v = Hc * (PI / 2.0 - phi) / PI - 0.5;
+    double fx = floor(u + 0.5);
+    fx -= Wc * floor(fx / Wc);
+    xi = (int)fx;
+    xi = xi >= Wc ? xi - Wc : (xi < 0 ? xi + Wc : xi);
+    const double fy = floor(v + 0.5);
+    yi = fy < 0.0 ? 0 : (fy > Hc - 1 ? Hc - 1 : (int)fy);
+}
+
+// The same decision from FP32 angles (atan2_full), taken only where it
+// provably equals the FP64 one: the FP32 pipeline (Y rounded to FP32,
+// atan2_full within 1e-6 rad of the angle, a few FP32 roundings of values
+// below Wc + 1) puts u + 1/2 within 3e-7 Wc + 1e-4 of its FP64 value, and
+// v + 1/2 within 3e-7 Hc + 1e-4, so when both lie farther than 4e-6 Wc +
+// 1e-3 (4e-6 Hc + 1e-3) from an integer, the floors agree. Otherwise, and
+// where the ray is too close to a pole for the FP32 lengths, it falls back
+// to nearest_pixel64: the result is that of the FP64 formulas.
+__device__ __forceinline__ void nearest_pixel(const double Y[3], int Wc, int Hc, int &xi, int &yi)
+{
+    const float y0 = (float)Y[0], y1 = (float)Y[1], y2 = (float)Y[2];
+    const float hz = __builtin_amdgcn_sqrtf(fmaf(y0, y0, y2 * y2));
+    const float lam = atan2_full(y0, y2), phi = atan2_full(-y1, hz);
+    const float fu = fmaf((float)Wc * 0.15915494f, lam, 0.5f * (float)Wc);
+    const float fv = fmaf(-(float)Hc * 0.31830989f, phi, 0.5f * (float)Hc);
+    const float gu = fmaf(4e-6f, (float)Wc, 1e-3f), gv = fmaf(4e-6f, (float)Hc, 1e-3f);
+    const float ru = fu - floorf(fu), rv = fv - floorf(fv);
+    if (!(hz > 1e-18f * fabsf(y1)) || !(ru > gu && ru < 1.0f - gu) || !(rv > gv && rv < 1.0f - gv)) {
+        nearest_pixel64(Y, Wc, Hc, xi, yi);
+        return;
+    }
+    int x = (int)floorf(fu);
+    x = x >= Wc ? x - Wc : (x < 0 ? x + Wc : x);
+    const int y = (int)floorf(fv);
+    xi = x;
+    yi = y < 0 ? 0 : (y > Hc - 1 ? Hc - 1 : y);
+}
+
 // Each valid source pixel claims the destination pixel nearest to the
 // projection of its plane point; the smallest key (nearest point, then the
 // lower source index) wins, so the outcome does not depend on the order of
@@ -1777,17 +1824,10 @@ __global__ __launch_bounds__(BLOCK) void k_warp_splat(WarpArgs A)
     warp_point(A, x, y, d, Y);
     const double range = sqrt(Y[0] * Y[0] + Y[1] * Y[1] + Y[2] * Y[2]);
     if (!(range > 0.0)) return;
-    const double PI = 3.14159265358979323846;
-    const double lam = atan2(Y[0], Y[2]);
-    const double phi = atan2(-Y[1], hypot(Y[0], Y[2]));
-    const double u = A.W * (lam + PI) / (2.0 * PI) - 0.5;
-    const double v = A.H * (PI / 2.0 - phi) / PI - 0.5;
-    double fx = floor(u + 0.5);
-    fx -= A.W * floor(fx / A.W);
-    int xi = (int)fx;
-    xi = xi >= A.W ? xi - A.W : (xi < 0 ? xi + A.W : xi);
-    const double fy = floor(v + 0.5);
-    const int yi = fy < 0.0 ? 0 : (fy > A.H - 1 ? A.H - 1 : (int)fy);
+    // (the guarded FP32 decision of nearest_pixel gained nothing here: the
+    // splat's time goes to its random 64-bit atomics)
+    int xi, yi;
+    nearest_pixel64(Y, A.W, A.H, xi, yi);
     if (yi < A.r || yi > A.H - 1 - A.r) return;
     const unsigned long long key =
         ((unsigned long long)__float_as_uint((float)range) << 32) | (unsigned long long)(unsigned)i;
@@ -2128,17 +2168,8 @@ __device__ __forceinline__ void cover_point(const FuseArgs &A, long long g)
 #pragma unroll
     for (int k = 0; k < 3; ++k) Y[k] = A.view.R[3 * k] * X[0] + A.view.R[3 * k + 1] * X[1] + A.view.R[3 * k + 2] * X[2] + A.view.t[k];
     if (!(Y[0] * Y[0] + Y[1] * Y[1] + Y[2] * Y[2] > 0.0)) return;
-    const double PI = 3.14159265358979323846;
-    const double lam = atan2(Y[0], Y[2]);
-    const double phi = atan2(-Y[1], hypot(Y[0], Y[2]));
-    const double u = A.Wc * (lam + PI) / (2.0 * PI) - 0.5;
-    const double v = A.Hc * (PI / 2.0 - phi) / PI - 0.5;
-    double fx = floor(u + 0.5);
-    fx -= A.Wc * floor(fx / A.Wc);
-    int xi = (int)fx;
-    xi = xi >= A.Wc ? xi - A.Wc : (xi < 0 ? xi + A.Wc : xi);
-    const double fy = floor(v + 0.5);
-    const int yi = fy < 0.0 ? 0 : (fy > A.Hc - 1 ? A.Hc - 1 : (int)fy);
+    int xi, yi;
+    nearest_pixel(Y, A.Wc, A.Hc, xi, yi);
     A.cover[(long long)yi * A.Wc + xi] = 1;
 }
 
