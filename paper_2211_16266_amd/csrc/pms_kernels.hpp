@@ -14,13 +14,15 @@
 //     handed out so that each XCD walks a contiguous band of rows and keeps
 //     the matching part of the neighbour images in its own L2.
 //   * Neighbour images are re-laid out once per call as bilinear cells (a
-//     corner value and its three differences, 16 bytes): every row is
-//     repeated around the seam to width 2W + 4 (columns -W/2-2 .. 3W/2+1),
-//     and the first and last rows are repeated once more above and below
-//     (the clamped pole taps). Any warped sample then reads its whole 2x2
-//     neighbourhood as one 16-byte buffer load at an offset from its
-//     anchor, with no seam or pole test; the offset is clamped to the
-//     storage, so no address can leave it whatever the inputs.
+//     corner value and its three differences in FP32, 16 bytes; 8 bytes of
+//     halves for FP16 and 8-bit images): every row is repeated around the
+//     seam to width 2W + 4 (columns -W/2-2 .. 3W/2+1), and the first and
+//     last rows are repeated once more above and below (the clamped pole
+//     taps). Any warped sample then reads its whole 2x2 neighbourhood as
+//     one buffer load at an offset from its anchor, with no seam or pole
+//     test; the buffer descriptor's range check (and, in the ragged-patch
+//     variants, a clamp of the offset) keeps every load inside the storage
+//     whatever the inputs.
 //   * Precision split: what is shared by all samples of one (pixel,
 //     hypothesis, view) -- relative pose, plane homography, anchor rotation,
 //     warped centre ray and its latitude offset -- is formed in FP64 (on
