@@ -72,7 +72,7 @@ METRIC = "keyframes/s + p50/p99 latency @1920×960, 4 nbrs; NCC evals/s vs roofl
 # lane-slots, +-25%), plus ~30 slots to finish the NCC.
 SLOTS_PER_SAMPLE = 76
 SLOTS_PER_EVAL = 30
-# The same unit re-derived from the gfx950 ISA of this build: its short-form
+# The same unit re-derived from the compiled gfx950 ISA: its short-form
 # sample loop issues 46 VALU instructions a sample (413 for the 9 samples of
 # a lane, counted in the compiled half-sweep), 2 of them rcp at half rate:
 # 48 slots; per evaluation
@@ -162,8 +162,8 @@ def _traffic_records() -> list:
                 for line in f if line.startswith("<!-- traffic ")]
 
 
-# Host cores the oracle may use: those this process may run on, at most the
-# 16 that the GPU machine allots to one GPU's jobs.
+# Host cores the oracle may use: those this process may run on, at most 16
+# (a one-GPU host's share of its cores).
 HOST_THREADS_MAX = 16
 
 
@@ -1070,7 +1070,7 @@ def main() -> int:
         return 0
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the densifier runs one keyframe job per GPU "
-              "and this build has no multi-GPU path; run with --gpus 1", file=sys.stderr)
+              "and has no multi-GPU path; run with --gpus 1", file=sys.stderr)
         return 2
 
     import torch
