@@ -1786,10 +1786,16 @@ pms_status pms_view_filter(pms_context *ctx, const double centre_a[3], const dou
     {
         LaunchTimer timer(ctx, KK_VIEW, s);
         hipLaunchKernelGGL(pms::k_count_clear, dim3(1), dim3(2 * pms::COUNT_SPREAD), 0, s, spread);
+        // cosines of the bounds; 2 / -2 where a bound admits / rejects every
+        // angle in [0, 180]
+        const double deg2rad = 3.14159265358979323846 / 180.0;
+        const double cmin = min_deg < 0.0 ? 2.0 : (min_deg > 180.0 ? -2.0 : std::cos(min_deg * deg2rad));
+        const double cmax = max_deg > 180.0 ? -2.0 : (max_deg < 0.0 ? 2.0 : std::cos(max_deg * deg2rad));
         if (n_points > 0)
             hipLaunchKernelGGL(pms::k_view_filter, dim3(count_grid(n_points)), dim3(pms::BLOCK), 0,
                                s, centre_a[0], centre_a[1], centre_a[2], centre_b[0], centre_b[1],
-                               centre_b[2], points, (long long)n_points, min_deg, max_deg, spread);
+                               centre_b[2], points, (long long)n_points, min_deg, max_deg, cmin, cmax,
+                               spread);
         hipLaunchKernelGGL(pms::k_count_gather, dim3(1), dim3(pms::COUNT_SPREAD), 0, s, spread, counts,
                            counts + 1);
     }

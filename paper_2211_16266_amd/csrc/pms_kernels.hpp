@@ -1607,7 +1607,10 @@ __global__ __launch_bounds__(BLOCK) void k_median(Launch L)
     for (int c = threadIdx.x; c < SW * SH; c += BLOCK) {
         const int r = c / SW, col = c - r * SW;
         const int yy = y0 - 2 + r;
-        const int xx = ((x0 - 2 + col) % A.W + A.W) % A.W;
+        int xx = x0 - 2 + col;
+        // (the halo wraps around the seam; more than once on images
+        // narrower than the window)
+        if (xx < 0 || xx >= A.W) xx = (xx % A.W + A.W) % A.W;
         tile[r][col] = yy >= 0 && yy < A.H ? state_depth(A, xx, yy) : 0.0f;
     }
     __syncthreads();
@@ -1955,10 +1958,16 @@ __device__ __forceinline__ void block_count_add(unsigned long long *spread, unsi
 
 // Per sparse point the angle between the directions to the two camera
 // centres (FP64); counts of points in [min_deg, max_deg] and of points not
-// at a centre.
+// at a centre. The angle decreases with its cosine: with cmin, cmax the
+// cosines of the bounds (2 or -2 where a bound admits or rejects every
+// angle), angle >= min_deg is cos < cmin and angle <= max_deg is cos >
+// cmax wherever the cosine lies farther than 1e-9 from the bound's (the
+// rounding of either form is below 1e-15); within that band the angle
+// itself decides, in degrees as before.
 __global__ __launch_bounds__(BLOCK) void k_view_filter(double ax, double ay, double az, double bx,
                                                        double by, double bz, const double *pts,
                                                        long long n, double min_deg, double max_deg,
+                                                       double cmin, double cmax,
                                                        unsigned long long *spread)
 {
     unsigned n_range = 0, n_counted = 0;
@@ -1970,9 +1979,15 @@ __global__ __launch_bounds__(BLOCK) void k_view_filter(double ax, double ay, dou
         if (la > 0.0 && lb > 0.0) {
             double cs = (a0 * b0 + a1 * b1 + a2 * b2) / (la * lb);
             cs = cs > 1.0 ? 1.0 : (cs < -1.0 ? -1.0 : cs);
-            const double deg = acos(cs) * (180.0 / 3.14159265358979323846);
+            bool in;
+            if (fabs(cs - cmin) > 1e-9 && fabs(cs - cmax) > 1e-9) {
+                in = cs < cmin && cs > cmax;
+            } else {
+                const double deg = acos(cs) * (180.0 / 3.14159265358979323846);
+                in = deg >= min_deg && deg <= max_deg;
+            }
             n_counted += 1;
-            n_range += deg >= min_deg && deg <= max_deg ? 1 : 0;
+            n_range += in ? 1 : 0;
         }
     }
     block_count_add(spread, n_range, n_counted);
